@@ -1,0 +1,192 @@
+/*
+ * ktruss.h — C-ABI of the MI355X (gfx950) Eager K-truss library.
+ *
+ * The method (Blanco, Low, Kim, "Exploration of Fine-Grained Parallelism for
+ * Load Balancing Eager K-truss on GPU and CPU", HPEC 2019):
+ *   - the K-truss is the largest edge set in which every edge lies in at least
+ *     K-2 triangles of the set (Section I);
+ *   - it is reached by repeating: compute every edge's support S (its triangle
+ *     count), keep the edges with S >= K-2, drop the rest, until a pass drops
+ *     nothing (Section II-A, Algorithm 1);
+ *   - supports are computed eagerly on the upper-triangular adjacency: each
+ *     triangle is found once, from its edge with the two smallest labels, and
+ *     increments all three edge supports; one fine-grained task per non-zero
+ *     (Section III-B, Algorithm 3).
+ *
+ * Conventions for every call:
+ *   - Return value: KTRUSS_OK (0) or a negative status code below.  No C++
+ *     exception crosses this boundary.  ktruss_last_error_message() returns a
+ *     thread-local description of the last failure on the calling thread.
+ *   - Graphs are upper-triangular CSR in 0-based int32: rowptr[n+1] with
+ *     rowptr[0] = 0 and rowptr[n] = m; col[m] with, inside row u, strictly
+ *     ascending columns all greater than u and less than n (exactly what
+ *     ktruss_build_csr produces).  Edge e is the e-th non-zero of that CSR
+ *     ("canonical position"); every per-edge output is indexed by it.
+ *   - Ownership: the caller owns every buffer.  Pointers marked "device" are
+ *     device memory of the current HIP device; "host" pointers are ordinary
+ *     host memory.  The library allocates no device memory: each graph call
+ *     works inside the caller's workspace (ktruss_workspace_bytes).
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream).  Calls enqueue work on it; calls that return host scalars
+ *     (ktruss_run's round count, ktruss_validate) synchronise that stream
+ *     before returning.  Two calls that share a workspace must not overlap.
+ */
+#ifndef KTRUSS_H
+#define KTRUSS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+#define KTRUSS_OK           0
+#define KTRUSS_E_INVALID   (-1)  /* null pointer, n < 0, K < 2, id outside [0,n), malformed CSR */
+#define KTRUSS_E_OVERFLOW  (-2)  /* n or m above INT32_MAX - 1 */
+#define KTRUSS_E_CAPACITY  (-3)  /* an output or workspace is too small; the needed size is reported */
+#define KTRUSS_E_HIP       (-4)  /* a HIP runtime call failed; see ktruss_last_hip_error() */
+#define KTRUSS_E_NOMEM     (-5)  /* host allocation failed */
+
+/* Support-kernel schedules (ktruss_graph.schedule).  They change speed only:
+ * mask, supports and round count are identical under every schedule. */
+#define KTRUSS_SCHED_PLAIN      0  /* every edge task on the thread-per-edge merge kernel */
+#define KTRUSS_SCHED_HEURISTIC  1  /* static degree heuristic bins rows/edges onto the kernel variants */
+#define KTRUSS_SCHED_LEARNED    2  /* MLP cost model bins rows/edges (falls back to HEURISTIC without weights) */
+#define KTRUSS_SCHED_FORCE_WAVE 3  /* every edge task on the wavefront-per-edge kernel (testing) */
+#define KTRUSS_SCHED_FORCE_HUB  4  /* every row on the workgroup-per-row kernel (testing) */
+
+/* Tuning knobs of the heuristic / learned schedules (0 = library default). */
+typedef struct ktruss_tuning {
+    int32_t wave_min_work;   /* edge tasks with estimated merge length >= this use wavefront-per-edge */
+    int32_t hub_min_work;    /* rows with total estimated work >= this use workgroup-per-row */
+    int32_t hub_chunk_work;  /* target work per workgroup when a hub row is split */
+    int32_t rounds_per_sync; /* prune rounds replayed (hipGraph) per host convergence check */
+    int32_t reserved[4];
+} ktruss_tuning;
+
+/* A graph resident on the device plus its workspace.  Caller-owned POD. */
+typedef struct ktruss_graph {
+    int32_t n;                 /* vertices */
+    int32_t schedule;          /* KTRUSS_SCHED_* */
+    int64_t m;                 /* edges (non-zeros of the upper triangle) */
+    const int32_t* rowptr;     /* device, n+1 */
+    const int32_t* col;        /* device, m */
+    void* work;                /* device, >= ktruss_workspace_bytes(n, m, 0) bytes */
+    int64_t work_bytes;
+    const float* mlp_params;   /* device, KTRUSS_MLP_PARAMS floats, or NULL (LEARNED schedule only) */
+    ktruss_tuning tuning;
+} ktruss_graph;
+
+/* ------------------------------------------------------------- diagnostics */
+const char* ktruss_strerror(int32_t code);
+/* Thread-local text of the last failure on this thread ("" if none). */
+const char* ktruss_last_error_message(void);
+/* The hipError_t of the last KTRUSS_E_HIP on this thread (0 if none). */
+int32_t ktruss_last_hip_error(void);
+/* Library version as major*10000 + minor*100 + patch. */
+int32_t ktruss_version(void);
+
+/* ------------------------------------------------------------- input prep */
+/*
+ * ktruss_build_csr — host only; the input preparation of Section IV-A (graphs
+ * are made upper-triangular), with the relabelling this library uses.
+ *   src, dst      host int32[npairs]: raw vertex pairs, read as undirected;
+ *                 self-loops and repeated pairs are dropped.
+ *   n             vertex count; every id must lie in [0, n).
+ *   order         0 keep ids; 1 relabel by ascending degree (ties: smaller
+ *                 original id first) — the default; 2 descending degree.
+ *   rowptr        host int32[n+1] out.
+ *   col           host int32[col_capacity] out; npairs entries always suffice.
+ *   new_to_old    host int32[n] out (new label -> original id), or NULL.
+ *   m_out         host int64 out: the edge count m (also set on E_CAPACITY).
+ * Errors: E_INVALID (null pointer, n < 0, npairs < 0, id outside [0,n),
+ * order outside 0..2), E_OVERFLOW (n or m > INT32_MAX-1), E_CAPACITY
+ * (col_capacity < m), E_NOMEM.
+ */
+int32_t ktruss_build_csr(const int32_t* src, const int32_t* dst, int64_t npairs, int32_t n,
+                         int32_t order, int32_t* rowptr, int32_t* col, int64_t col_capacity,
+                         int32_t* new_to_old, int64_t* m_out);
+
+/* ---------------------------------------------------------------- device */
+/*
+ * ktruss_workspace_bytes — device workspace needed by ktruss_validate,
+ * ktruss_support and ktruss_run on a graph with n vertices and m edges
+ * (flags must be 0).  Returns a negative status on invalid sizes.
+ */
+int64_t ktruss_workspace_bytes(int32_t n, int64_t m, int32_t flags);
+
+/*
+ * ktruss_validate — checks on the device that g's CSR has the canonical form
+ * described above.  Synchronises `stream`.  KTRUSS_OK or E_INVALID.
+ * ktruss_support and ktruss_run perform the same check first.
+ */
+int32_t ktruss_validate(const ktruss_graph* g, void* stream);
+
+/*
+ * ktruss_support — one evaluation of S = (A^T A) o A (Algorithm 1, first line
+ * of the loop) on the alive subgraph, by eager fine-grained tasks (Algorithm 3).
+ *   alive    device uint8[m]: non-zero = edge present; NULL = every edge.
+ *   support  device int32[m] out: triangles of the alive subgraph containing
+ *            edge e if e is alive, else 0.
+ * Stateless.  Synchronises `stream` once (input validation).
+ */
+int32_t ktruss_support(const ktruss_graph* g, const uint8_t* alive, int32_t* support, void* stream);
+
+/*
+ * ktruss_prune — Algorithm 1's mask and update lines: alive[e] stays non-zero
+ * iff it was non-zero and support[e] >= K-2.
+ *   K        >= 2.
+ *   support  device int32[m] in.
+ *   alive    device uint8[m] in/out (output values are 0/1).
+ *   removed  device int64 out (may be NULL): number of edges switched off.
+ * Stateless, asynchronous; does not use the workspace.
+ */
+int32_t ktruss_prune(const ktruss_graph* g, int32_t K, const int32_t* support, uint8_t* alive,
+                     int64_t* removed, void* stream);
+
+/*
+ * ktruss_run — the whole fixpoint of Algorithm 1: supports, prune, repeat
+ * until a pass removes nothing.
+ *   K        >= 2.
+ *   mask     device uint8[m] out: 1 iff edge e is in the K-truss.
+ *   support  device int32[m] out: e's support inside the K-truss, 0 if removed.
+ *   rounds   host int32 out (may be NULL): number of support passes, counting
+ *            the final pass that removes nothing.
+ * Equal, bit for bit, to iterating ktruss_support / ktruss_prune to a
+ * fixpoint.  Synchronises `stream`.
+ */
+int32_t ktruss_run(const ktruss_graph* g, int32_t K, uint8_t* mask, int32_t* support,
+                   int32_t* rounds, void* stream);
+
+/*
+ * ktruss_set_schedule — selects the support-kernel schedule of g (sets
+ * g->schedule, g->mlp_params and, if t is not NULL, g->tuning).  Results do
+ * not depend on it.  E_INVALID for an unknown mode.
+ */
+int32_t ktruss_set_schedule(ktruss_graph* g, int32_t mode, const float* mlp_params,
+                            const ktruss_tuning* t);
+
+/* ------------------------------------------------------------- profiling */
+/*
+ * Kernel timing, a measurement aid.  While enabled (on != 0), every support
+ * kernel launch issued by ktruss_support / ktruss_run on this process is
+ * bracketed by HIP events recorded on the call's stream, and its work is
+ * tallied: edge tasks (alive edges of that pass) and compulsory bytes
+ * (16 per edge task: its column, its row and one read plus one write of its
+ * support word; plus 4 per row pointer).  Enabling clears the tallies.
+ * Returns KTRUSS_OK.
+ */
+int32_t ktruss_profile_enable(int32_t on);
+/*
+ * Reads the tallies since the last enable: launches, summed kernel time in
+ * milliseconds (synchronises on the recorded events), edge tasks and
+ * compulsory bytes.  Any out pointer may be NULL.
+ */
+int32_t ktruss_profile_read(int64_t* launches, double* total_ms, int64_t* edge_tasks, int64_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KTRUSS_H */

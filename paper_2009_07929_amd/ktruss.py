@@ -1,0 +1,207 @@
+"""Thin Python binding of the C-ABI in include/ktruss.h (ctypes).
+
+Argument marshalling only: every step of the K-truss path runs in the HIP
+library.  Device buffers are torch tensors on the current HIP device (torch is
+used for device memory and streams); the calls take the same names as the C
+functions.  If libktruss.so cannot be loaded the import fails loudly — there is
+no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+# status codes (include/ktruss.h)
+OK, E_INVALID, E_OVERFLOW, E_CAPACITY, E_HIP, E_NOMEM = 0, -1, -2, -3, -4, -5
+SCHED_PLAIN, SCHED_HEURISTIC, SCHED_LEARNED, SCHED_FORCE_WAVE, SCHED_FORCE_HUB = 0, 1, 2, 3, 4
+
+_lib = None
+
+
+class KtrussError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__("%s (%d): %s" % (_strerror(code), code, message))
+        self.code = code
+
+
+class ktruss_tuning(ctypes.Structure):
+    _fields_ = [("wave_min_work", ctypes.c_int32), ("hub_min_work", ctypes.c_int32),
+                ("hub_chunk_work", ctypes.c_int32), ("rounds_per_sync", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
+
+
+class ktruss_graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("schedule", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("work", ctypes.c_void_p),
+                ("work_bytes", ctypes.c_int64), ("mlp_params", ctypes.c_void_p), ("tuning", ktruss_tuning)]
+
+
+def library_path() -> str:
+    return _build.LIB
+
+
+def load():
+    """Load libktruss.so (building it with hipcc only if it does not exist yet)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_build.LIB):
+        _build.build_library(force=False)
+    lib = ctypes.CDLL(_build.LIB)
+    i32, i64, p = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+    G = ctypes.POINTER(ktruss_graph)
+    sig = {
+        "ktruss_strerror": ([i32], ctypes.c_char_p),
+        "ktruss_last_error_message": ([], ctypes.c_char_p),
+        "ktruss_last_hip_error": ([], i32),
+        "ktruss_version": ([], i32),
+        "ktruss_build_csr": ([p, p, i64, i32, i32, p, p, i64, p, p], i32),
+        "ktruss_workspace_bytes": ([i32, i64, i32], i64),
+        "ktruss_validate": ([G, p], i32),
+        "ktruss_support": ([G, p, p, p], i32),
+        "ktruss_prune": ([G, i32, p, p, p, p], i32),
+        "ktruss_run": ([G, i32, p, p, p, p], i32),
+        "ktruss_set_schedule": ([G, i32, p, ctypes.POINTER(ktruss_tuning)], i32),
+        "ktruss_profile_enable": ([i32], i32),
+        "ktruss_profile_read": ([p, p, p, p], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _strerror(code):
+    try:
+        return load().ktruss_strerror(code).decode()
+    except Exception:
+        return "status"
+
+
+def _check(rc):
+    if rc != OK:
+        raise KtrussError(rc, load().ktruss_last_error_message().decode())
+    return rc
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data
+    return t.data_ptr()
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def ktruss_build_csr(src, dst, n: int, order: int = 1):
+    """Host CSR builder: (rowptr int32[n+1], col int32[m], new_to_old int32[n]) as NumPy arrays."""
+    src = np.ascontiguousarray(src, np.int32)
+    dst = np.ascontiguousarray(dst, np.int32)
+    if src.shape != dst.shape:
+        raise ValueError("src and dst differ in length")
+    rowptr = np.empty(n + 1, np.int32)
+    col = np.empty(max(len(src), 1), np.int32)
+    n2o = np.empty(max(n, 1), np.int32)
+    m = ctypes.c_int64()
+    _check(load().ktruss_build_csr(_ptr(src), _ptr(dst), len(src), n, order, _ptr(rowptr), _ptr(col),
+                                   len(col), _ptr(n2o), ctypes.byref(m)))
+    return rowptr, col[: m.value].copy(), n2o[:n].copy()
+
+
+def ktruss_workspace_bytes(n: int, m: int, flags: int = 0) -> int:
+    r = load().ktruss_workspace_bytes(n, m, flags)
+    if r < 0:
+        _check(int(r))
+    return int(r)
+
+
+class Graph:
+    """A device-resident CSR graph with its workspace (owns the torch tensors)."""
+
+    def __init__(self, rowptr, col, device="cuda", schedule=SCHED_PLAIN):
+        import torch
+        rowptr = torch.as_tensor(np.ascontiguousarray(rowptr, np.int32) if isinstance(rowptr, np.ndarray) else rowptr)
+        col = torch.as_tensor(np.ascontiguousarray(col, np.int32) if isinstance(col, np.ndarray) else col)
+        self.n = int(rowptr.numel()) - 1
+        self.m = int(col.numel())
+        self.rowptr = rowptr.to(device=device, dtype=torch.int32).contiguous()
+        self.col = (col if self.m else torch.zeros(1, dtype=torch.int32)).to(device=device, dtype=torch.int32).contiguous()
+        nbytes = ktruss_workspace_bytes(self.n, self.m)
+        self.work = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.mlp_params = None
+        self.c = ktruss_graph()
+        self.c.n = self.n
+        self.c.m = self.m
+        self.c.schedule = schedule
+        self.c.rowptr = self.rowptr.data_ptr()
+        self.c.col = self.col.data_ptr()
+        self.c.work = self.work.data_ptr()
+        self.c.work_bytes = nbytes
+        self.c.mlp_params = None
+
+    @property
+    def device(self):
+        return self.rowptr.device
+
+
+def ktruss_set_schedule(g: Graph, mode: int, mlp_params=None, tuning: ktruss_tuning | None = None):
+    g.mlp_params = mlp_params
+    _check(load().ktruss_set_schedule(ctypes.byref(g.c), mode, _ptr(mlp_params),
+                                      ctypes.byref(tuning) if tuning is not None else None))
+
+
+def ktruss_validate(g: Graph, stream=None):
+    _check(load().ktruss_validate(ctypes.byref(g.c), _stream(stream)))
+
+
+def ktruss_support(g: Graph, alive=None, support=None, stream=None):
+    """One support evaluation on the alive subgraph; returns support int32[m] (device)."""
+    import torch
+    if support is None:
+        support = torch.empty(max(g.m, 1), dtype=torch.int32, device=g.device)
+    _check(load().ktruss_support(ctypes.byref(g.c), _ptr(alive), _ptr(support), _stream(stream)))
+    return support[: g.m]
+
+
+def ktruss_prune(g: Graph, K: int, support, alive, removed=None, stream=None):
+    """alive &= support >= K-2 in place; `removed` (int64[1] device tensor) gets the count."""
+    _check(load().ktruss_prune(ctypes.byref(g.c), K, _ptr(support), _ptr(alive), _ptr(removed), _stream(stream)))
+    return alive
+
+
+def ktruss_profile_enable(on: bool = True):
+    _check(load().ktruss_profile_enable(1 if on else 0))
+
+
+def ktruss_profile_read():
+    """(launches, total_ms, edge_tasks, compulsory_bytes) of the timed support launches."""
+    launches, edges, nbytes = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check(load().ktruss_profile_read(ctypes.byref(launches), ctypes.byref(ms), ctypes.byref(edges),
+                                      ctypes.byref(nbytes)))
+    return launches.value, ms.value, edges.value, nbytes.value
+
+
+def ktruss_run(g: Graph, K: int, mask=None, support=None, stream=None):
+    """Full fixpoint.  Returns (mask uint8[m], support int32[m], rounds)."""
+    import torch
+    if mask is None:
+        mask = torch.empty(max(g.m, 1), dtype=torch.uint8, device=g.device)
+    if support is None:
+        support = torch.empty(max(g.m, 1), dtype=torch.int32, device=g.device)
+    rounds = ctypes.c_int32()
+    _check(load().ktruss_run(ctypes.byref(g.c), K, _ptr(mask), _ptr(support), ctypes.byref(rounds),
+                             _stream(stream)))
+    return mask[: g.m], support[: g.m], rounds.value

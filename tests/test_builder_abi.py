@@ -1,0 +1,134 @@
+"""Host-side checks that need no GPU: the library loads and exports every
+symbol include/ktruss.h declares; the host CSR builder equals the oracle's own
+canonicalisation; argument errors come back as status codes before any HIP call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_2009_07929_amd import ktruss as kt
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "ktruss.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ktruss_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    lib = kt.load()
+    names = declared_functions()
+    assert "ktruss_run" in names and "ktruss_build_csr" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert kt.load().ktruss_version() >= 100
+
+
+def test_strerror():
+    lib = kt.load()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.ktruss_strerror(code)
+
+
+@pytest.mark.parametrize("order", [0, 1, 2])
+@pytest.mark.parametrize("which", ["noise", "rmat", "star", "empty"])
+def test_builder_equals_oracle(order, which):
+    g = {"noise": synth.raw_noise(500, 5000, 9), "rmat": synth.rmat(12, 8, 0.57, 0.19, 0.19, 1),
+         "star": synth.star(50), "empty": (7, np.zeros(0, np.int32), np.zeros(0, np.int32))}[which]
+    n, s, d = g
+    rp, col, n2o = kt.ktruss_build_csr(s, d, n, order)
+    orp, ocol, on2o = oracle.canonical_csr(n, s, d, order)
+    assert np.array_equal(rp, orp) and np.array_equal(col, ocol) and np.array_equal(n2o, on2o)
+
+
+def test_builder_self_loops_and_duplicates():
+    s = np.array([0, 1, 1, 2, 2, 3, 3], np.int32)
+    d = np.array([0, 2, 2, 1, 3, 3, 1], np.int32)
+    rp, col, n2o = kt.ktruss_build_csr(s, d, 5, 0)
+    assert rp.tolist() == [0, 0, 2, 3, 3, 3] and col.tolist() == [2, 3, 3]
+
+
+def test_builder_errors():
+    s = np.array([0, 5], np.int32)
+    d = np.array([1, 2], np.int32)
+    with pytest.raises(kt.KtrussError) as ei:
+        kt.ktruss_build_csr(s, d, 5)
+    assert ei.value.code == kt.E_INVALID
+    with pytest.raises(kt.KtrussError) as ei:
+        kt.ktruss_build_csr(np.array([0], np.int32), np.array([1], np.int32), 2, order=7)
+    assert ei.value.code == kt.E_INVALID
+    lib = kt.load()
+    rp = np.zeros(4, np.int32)
+    col = np.zeros(1, np.int32)
+    m = ctypes.c_int64()
+    s3 = np.array([0, 1, 0], np.int32)
+    d3 = np.array([1, 2, 2], np.int32)
+    rc = lib.ktruss_build_csr(s3.ctypes.data, d3.ctypes.data, 3, 3, 1, rp.ctypes.data, col.ctypes.data, 1, None,
+                              ctypes.byref(m))
+    assert rc == kt.E_CAPACITY and m.value == 3
+    rc = lib.ktruss_build_csr(None, None, 3, 3, 1, rp.ctypes.data, col.ctypes.data, 3, None, ctypes.byref(m))
+    assert rc == kt.E_INVALID
+    rc = lib.ktruss_build_csr(s3.ctypes.data, d3.ctypes.data, 3, -1, 1, rp.ctypes.data, col.ctypes.data, 3, None,
+                              ctypes.byref(m))
+    assert rc == kt.E_INVALID
+
+
+def test_workspace_bytes():
+    assert kt.ktruss_workspace_bytes(10, 20) > 0
+    assert kt.load().ktruss_workspace_bytes(-1, 0, 0) == kt.E_INVALID
+    assert kt.load().ktruss_workspace_bytes(1, 2**31, 0) == kt.E_OVERFLOW
+    assert kt.load().ktruss_workspace_bytes(1, 1, 3) == kt.E_INVALID
+    big = kt.ktruss_workspace_bytes(1000, 100000)
+    assert big >= 36 * 100000
+
+
+def host_graph(n=4, m=3, work_bytes=None):
+    g = kt.ktruss_graph()
+    g.n = n
+    g.m = m
+    g.rowptr = 16
+    g.col = 16
+    g.work = 256
+    g.work_bytes = kt.ktruss_workspace_bytes(n, m) if work_bytes is None else work_bytes
+    return g
+
+
+def test_argument_errors_before_any_hip_call():
+    lib = kt.load()
+    G = ctypes.byref
+    assert lib.ktruss_run(None, 3, 16, 16, None, None) == kt.E_INVALID
+    g = host_graph()
+    assert lib.ktruss_run(G(g), 1, 16, 16, None, None) == kt.E_INVALID            # K < 2
+    assert lib.ktruss_run(G(g), 3, None, 16, None, None) == kt.E_INVALID          # null mask
+    g2 = host_graph(work_bytes=10)
+    assert lib.ktruss_run(G(g2), 3, 16, 16, None, None) == kt.E_CAPACITY
+    assert b"needs" in lib.ktruss_last_error_message()
+    g3 = host_graph()
+    g3.schedule = 17
+    assert lib.ktruss_support(G(g3), None, 16, None) == kt.E_INVALID
+    g4 = host_graph()
+    g4.n = -3
+    assert lib.ktruss_prune(G(g4), 3, 16, 16, None, None) == kt.E_INVALID
+    g5 = host_graph()
+    g5.m = 2**31
+    assert lib.ktruss_run(G(g5), 3, 16, 16, None, None) == kt.E_OVERFLOW
+    assert lib.ktruss_prune(G(host_graph()), 1, 16, 16, None, None) == kt.E_INVALID
+    assert lib.ktruss_set_schedule(G(host_graph()), 9, None, None) == kt.E_INVALID
+    assert lib.ktruss_set_schedule(None, 0, None, None) == kt.E_INVALID
+    g6 = host_graph()
+    g6.work = 257                                                                   # misaligned workspace
+    assert lib.ktruss_validate(G(g6), None) == kt.E_INVALID
+
+
+def test_set_schedule_fields():
+    g = host_graph()
+    t = kt.ktruss_tuning()
+    t.wave_min_work = 123
+    assert kt.load().ktruss_set_schedule(ctypes.byref(g), kt.SCHED_HEURISTIC, None, ctypes.byref(t)) == 0
+    assert g.schedule == kt.SCHED_HEURISTIC and g.tuning.wave_min_work == 123
