@@ -128,7 +128,12 @@ def main():
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    launches, sup_ms, edge_tasks, nbytes = kt.ktruss_profile_read()
+    launches, sup_ms, edge_tasks, nbytes = kt.ktruss_profile_read(kt.PROFILE_PASS)
+    kinds = {}
+    for name, kind in (("thread", kt.PROFILE_THREAD), ("wave", kt.PROFILE_WAVE), ("hub", kt.PROFILE_HUB)):
+        nl, ms, tasks, _ = kt.ktruss_profile_read(kind)
+        if nl:
+            kinds[name] = {"launches": nl, "ms": ms, "tasks": tasks}
     kt.ktruss_profile_enable(False)
     log("timed %d steps in %.3fs" % (args.steps, elapsed))
 
@@ -158,7 +163,7 @@ def main():
         "config": {"workload": args.workload, "n": n, "m": m, "Ks": list(Ks), "schedule": args.schedule,
                    "per_K": per_k},
         "roofline": {
-            "kernel": "support",
+            "kernel": "support pass",
             "bound": "hbm",
             "achieved": achieved,
             "peak": PEAK_HBM_GBPS,
@@ -168,6 +173,7 @@ def main():
             "launches": launches,
             "avg_launch_ms": avg_launch_ms,
             "support_share_of_step": sup_ms / (elapsed * 1e3),
+            "variants": kinds,
         },
         "cpu_baseline": cpu,
     }

@@ -169,21 +169,23 @@ int32_t ktruss_set_schedule(ktruss_graph* g, int32_t mode, const float* mlp_para
 
 /* ------------------------------------------------------------- profiling */
 /*
- * Kernel timing, a measurement aid.  While enabled (on != 0), every support
- * kernel launch issued by ktruss_support / ktruss_run on this process is
- * bracketed by HIP events recorded on the call's stream, and its work is
- * tallied: edge tasks (alive edges of that pass) and compulsory bytes
- * (16 per edge task: its column, its row and one read plus one write of its
- * support word; plus 4 per row pointer).  Enabling clears the tallies.
- * Returns KTRUSS_OK.
+ * Kernel timing, a measurement aid.  While enabled (on != 0), the support
+ * launches issued by ktruss_support / ktruss_run in this process are bracketed
+ * by HIP events recorded on the call's stream and tallied by kind:
+ *   0  the whole support pass (all variants of one pass), 16 compulsory bytes
+ *      per alive edge (its column, its row, one read and one write of its
+ *      support word) plus 4 per row pointer;
+ *   1  thread-per-edge launches, 2 wavefront-per-edge launches, 3 hub-row
+ *      launches (tasks = edge tasks, or hub items for kind 3).
+ * Enabling (or disabling) clears the tallies.  Returns KTRUSS_OK.
  */
 int32_t ktruss_profile_enable(int32_t on);
 /*
- * Reads the tallies since the last enable: launches, summed kernel time in
- * milliseconds (synchronises on the recorded events), edge tasks and
- * compulsory bytes.  Any out pointer may be NULL.
+ * Reads the tallies of `kind` since the last enable: launches, summed time in
+ * milliseconds (synchronises on the recorded events), tasks and compulsory
+ * bytes.  Any out pointer may be NULL.  E_INVALID for a kind outside 0..3.
  */
-int32_t ktruss_profile_read(int64_t* launches, double* total_ms, int64_t* edge_tasks, int64_t* bytes);
+int32_t ktruss_profile_read(int32_t kind, int64_t* launches, double* total_ms, int64_t* tasks, int64_t* bytes);
 
 #ifdef __cplusplus
 }

@@ -192,55 +192,22 @@ static int check_csr(int32_t n, const int32_t* rowptr, const int32_t* col) {
     return ORC_OK;
 }
 
-/* Position of neighbour x in the sorted list a->nbr[lo, hi), or -1. */
-static int64_t find_nbr(const sym_adj* a, int64_t lo, int64_t hi, int32_t x) {
-    const int64_t end = hi;
-    while (lo < hi) {
-        const int64_t mid = lo + (hi - lo) / 2;
-        if (a->nbr[mid] < x) lo = mid + 1;
-        else hi = mid;
-    }
-    return (lo < end && a->nbr[lo] == x) ? lo : -1;
-}
-
 /* Calls visit(ctx, e1, e2) for every common neighbour w of u and v, where e1
- * is the edge (u,w) and e2 the edge (v,w).  Two sorted lists are intersected
- * either by a merge, or, when one is much longer, by looking up each element
- * of the shorter list with a binary search in the longer one — whichever
- * touches fewer entries; both visit exactly the common neighbours. */
+ * is the edge (u,w) and e2 the edge (v,w): a merge of the two sorted lists. */
 typedef void (*visit_fn)(void* ctx, int64_t e1, int64_t e2);
 
-static int log2_ceil(int64_t x) {
-    int b = 0;
-    while (((int64_t)1 << b) < x) ++b;
-    return b;
-}
-
 static void for_common(const sym_adj* a, int32_t u, int32_t v, visit_fn visit, void* ctx) {
-    const int64_t du = a->off[u + 1] - a->off[u], dv = a->off[v + 1] - a->off[v];
-    const int64_t dmin = du < dv ? du : dv, dmax = du < dv ? dv : du;
-    if (dmin * (log2_ceil(dmax) + 1) >= du + dv) {
-        int64_t p = a->off[u], pe = a->off[u + 1];
-        int64_t q = a->off[v], qe = a->off[v + 1];
-        while (p < pe && q < qe) {
-            const int32_t x = a->nbr[p], y = a->nbr[q];
-            if (x < y) ++p;
-            else if (y < x) ++q;
-            else {
-                visit(ctx, a->eid[p], a->eid[q]);
-                ++p;
-                ++q;
-            }
+    int64_t p = a->off[u], pe = a->off[u + 1];
+    int64_t q = a->off[v], qe = a->off[v + 1];
+    while (p < pe && q < qe) {
+        const int32_t x = a->nbr[p], y = a->nbr[q];
+        if (x < y) ++p;
+        else if (y < x) ++q;
+        else {
+            visit(ctx, a->eid[p], a->eid[q]);
+            ++p;
+            ++q;
         }
-        return;
-    }
-    int32_t s = u, l = v;
-    if (du > dv) { s = v; l = u; }
-    for (int64_t p = a->off[s]; p < a->off[s + 1]; ++p) {
-        const int64_t q = find_nbr(a, a->off[l], a->off[l + 1], a->nbr[p]);
-        if (q < 0) continue;
-        if (s == u) visit(ctx, a->eid[p], a->eid[q]);
-        else visit(ctx, a->eid[q], a->eid[p]);
     }
 }
 

@@ -44,6 +44,7 @@ Layout layout(int32_t n, int64_t m) {
         return o;
     };
     const size_t em = sizeof(int32_t) * (size_t)m;
+    const size_t em1 = sizeof(int32_t) * ((size_t)m + 1);
     const size_t vn = sizeof(int32_t) * ((size_t)n + 1);
     for (int b = 0; b < 2; ++b) {
         L.col[b] = take(em);
@@ -51,10 +52,22 @@ Layout layout(int32_t n, int64_t m) {
         L.eid[b] = take(em);
         L.S[b] = take(em);
         L.rowptr[b] = take(vn);
+        L.cedge[b] = take(em);
+        L.cptr[b] = take(vn);
     }
-    L.xscan = take(sizeof(int32_t) * ((size_t)m + 1));
+    L.xscan = take(em1);
+    L.cxscan = take(em1);
     L.blockcnt = take(sizeof(int32_t) * kMaxScanBlocks);
     L.blockoff = take(sizeof(int32_t) * kMaxScanBlocks);
+    L.blockcnt2 = take(sizeof(int32_t) * 2 * kMaxScanBlocks);
+    L.blockoff2 = take(sizeof(int32_t) * 2 * kMaxScanBlocks);
+    L.tmp_n = take(vn);
+    L.itemoff = take(vn);
+    L.item_kappa = take(sizeof(int32_t) * (size_t)item_capacity(n, m));
+    L.item_c0 = take(sizeof(int32_t) * (size_t)item_capacity(n, m));
+    L.is_hub = take((size_t)n + 1);
+    L.wave_tasks = take(em);
+    L.thread_tasks = take(em);
     L.ctl = take(sizeof(Ctl));
     L.total = off;
     return L;
@@ -64,9 +77,8 @@ namespace {
 
 struct Work {
     Buf b[2];
-    int32_t* xscan;
-    int32_t* blockcnt;
-    int32_t* blockoff;
+    Csc c[2];
+    Scratch sc;
     Ctl* ctl;
 };
 
@@ -80,10 +92,22 @@ Work carve(const ktruss_graph* g) {
         w.b[b].eid = (int32_t*)(base + L.eid[b]);
         w.b[b].S = (int32_t*)(base + L.S[b]);
         w.b[b].rowptr = (int32_t*)(base + L.rowptr[b]);
+        w.c[b].edge = (int32_t*)(base + L.cedge[b]);
+        w.c[b].ptr = (int32_t*)(base + L.cptr[b]);
     }
-    w.xscan = (int32_t*)(base + L.xscan);
-    w.blockcnt = (int32_t*)(base + L.blockcnt);
-    w.blockoff = (int32_t*)(base + L.blockoff);
+    w.sc.xscan = (int32_t*)(base + L.xscan);
+    w.sc.cxscan = (int32_t*)(base + L.cxscan);
+    w.sc.blockcnt = (int32_t*)(base + L.blockcnt);
+    w.sc.blockoff = (int32_t*)(base + L.blockoff);
+    w.sc.blockcnt2 = (int32_t*)(base + L.blockcnt2);
+    w.sc.blockoff2 = (int32_t*)(base + L.blockoff2);
+    w.sc.tmp_n = (int32_t*)(base + L.tmp_n);
+    w.sc.itemoff = (int32_t*)(base + L.itemoff);
+    w.sc.item_kappa = (int32_t*)(base + L.item_kappa);
+    w.sc.item_c0 = (int32_t*)(base + L.item_c0);
+    w.sc.is_hub = (uint8_t*)(base + L.is_hub);
+    w.sc.wave_tasks = (int32_t*)(base + L.wave_tasks);
+    w.sc.thread_tasks = (int32_t*)(base + L.thread_tasks);
     w.ctl = (Ctl*)(base + L.ctl);
     return w;
 }
@@ -129,13 +153,19 @@ int32_t validate_on_device(const ktruss_graph* g, const Work& w, int32_t* src_ou
 }
 
 // ---- profiling tallies (process-wide; guarded by a mutex)
+// kinds: 0 whole support pass, 1 thread-per-edge, 2 wavefront-per-edge, 3 hub
+constexpr int kKinds = 4;
+struct Rec {
+    int kind;
+    hipEvent_t e0, e1;
+};
 struct Profile {
     std::mutex mu;
     bool on = false;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> events;  // recorded, not yet read
+    std::vector<Rec> recs;  // recorded, not yet read
     std::vector<hipEvent_t> pool;
-    int64_t launches = 0, edge_tasks = 0, bytes = 0;
-    double ms = 0.0;
+    int64_t launches[kKinds] = {}, tasks[kKinds] = {}, bytes[kKinds] = {};
+    double ms[kKinds] = {};
 };
 Profile& prof() {
     static Profile p;
@@ -153,31 +183,97 @@ hipEvent_t take_event(Profile& P) {
     return e;
 }
 
-// One support pass over buffer p (m_hint alive edges, known on the host).
-int32_t support_pass(const ktruss_graph* g, const Work& w, int p, int32_t m_hint, hipStream_t s) {
-    Profile& P = prof();
+// Event pair around a group of launches, tallied under `kind` when profiling.
+struct Timer {
+    bool on = false;
+    int kind = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    bool timed = false;
+};
+
+int32_t timer_begin(Timer& t, int kind, int64_t tasks, int64_t bytes, hipStream_t s) {
+    Profile& P = prof();
     {
         std::lock_guard<std::mutex> lk(P.mu);
-        if (P.on) {
-            e0 = take_event(P);
-            e1 = take_event(P);
-            timed = e0 && e1;
-            if (timed) {
-                P.launches += 1;
-                P.edge_tasks += m_hint;
-                P.bytes += 16 * (int64_t)m_hint + 4 * ((int64_t)g->n + 1);
-            }
+        if (!P.on) return KTRUSS_OK;
+        t.e0 = take_event(P);
+        t.e1 = take_event(P);
+        if (!t.e0 || !t.e1) return fail(KTRUSS_E_HIP, "hipEventCreate failed");
+        P.launches[kind] += 1;
+        P.tasks[kind] += tasks;
+        P.bytes[kind] += bytes;
+    }
+    t.on = true;
+    t.kind = kind;
+    HIP_TRY(hipEventRecord(t.e0, s), "profile event");
+    return KTRUSS_OK;
+}
+
+int32_t timer_end(Timer& t, hipStream_t s) {
+    if (!t.on) return KTRUSS_OK;
+    HIP_TRY(hipEventRecord(t.e1, s), "profile event");
+    Profile& P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.recs.push_back(Rec{t.kind, t.e0, t.e1});
+    return KTRUSS_OK;
+}
+
+template <class F>
+int32_t timed_launch(int kind, int64_t tasks, hipStream_t s, F&& launch) {
+    if (tasks <= 0) return KTRUSS_OK;
+    Timer t;
+    int32_t rc = timer_begin(t, kind, tasks, 16 * tasks, s);
+    if (rc != KTRUSS_OK) return rc;
+    HIP_TRY(launch(), "support launch");
+    return timer_end(t, s);
+}
+
+bool uses_csc(int sched) { return sched != KTRUSS_SCHED_PLAIN && sched != KTRUSS_SCHED_FORCE_WAVE; }
+
+// One support pass over buffer p.  h holds the host copy of the control
+// block after the pass was prepared (task and item counts).
+int32_t support_pass(const ktruss_graph* g, const Work& w, int p, int32_t m_hint, const Ctl& h, hipStream_t s) {
+    const int sched = g->schedule;
+    const Buf& x = w.b[p];
+    Timer tp;
+    int32_t rc = timer_begin(tp, 0, m_hint, 16 * (int64_t)m_hint + 4 * ((int64_t)g->n + 1), s);
+    if (rc != KTRUSS_OK) return rc;
+    if (sched == KTRUSS_SCHED_PLAIN) {
+        rc = timed_launch(1, m_hint, s, [&] {
+            return launch_support_thread(x, nullptr, &w.ctl->m_buf[p], m_hint, w.ctl, s);
+        });
+    } else if (sched == KTRUSS_SCHED_FORCE_WAVE) {
+        rc = timed_launch(2, m_hint, s, [&] {
+            return launch_support_wave(x, nullptr, &w.ctl->m_buf[p], m_hint, w.ctl, s);
+        });
+    } else {
+        rc = timed_launch(3, h.n_items, s, [&] {
+            return launch_support_hub(x, w.c[p], w.sc.item_kappa, w.sc.item_c0, h.n_items, w.ctl, s);
+        });
+        if (rc == KTRUSS_OK && sched != KTRUSS_SCHED_FORCE_HUB) {
+            rc = timed_launch(2, h.n_wave, s, [&] {
+                return launch_support_wave(x, w.sc.wave_tasks, &w.ctl->n_wave, h.n_wave, w.ctl, s);
+            });
+            if (rc == KTRUSS_OK)
+                rc = timed_launch(1, h.n_thread, s, [&] {
+                    return launch_support_thread(x, w.sc.thread_tasks, &w.ctl->n_thread, h.n_thread, w.ctl, s);
+                });
         }
     }
-    if (timed) HIP_TRY(hipEventRecord(e0, s), "profile event");
-    HIP_TRY(launch_support_thread_edge(w.b[p], w.ctl, p, m_hint, s), "support launch");
-    if (timed) {
-        HIP_TRY(hipEventRecord(e1, s), "profile event");
-        std::lock_guard<std::mutex> lk(P.mu);
-        P.events.emplace_back(e0, e1);
-    }
+    if (rc != KTRUSS_OK) return rc;
+    return timer_end(tp, s);
+}
+
+int32_t read_ctl(const Work& w, Ctl& h, hipStream_t s) {
+    HIP_TRY(hipMemcpyAsync(&h, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "control readback");
+    HIP_TRY(hipStreamSynchronize(s), "control sync");
+    return KTRUSS_OK;
+}
+
+int32_t prepare(const ktruss_graph* g, const Work& w, int p, int32_t m_hint, hipStream_t s) {
+    if (!uses_csc(g->schedule)) return KTRUSS_OK;
+    Scratch sc = w.sc;
+    HIP_TRY(launch_prepare_pass(w.b[p], w.c[p], g->n, g->schedule, g->tuning, nullptr, sc, w.ctl, p, m_hint, s),
+            "prepare pass");
     return KTRUSS_OK;
 }
 
@@ -216,36 +312,39 @@ int32_t ktruss_profile_enable(int32_t on) {
     clear_error();
     Profile& P = prof();
     std::lock_guard<std::mutex> lk(P.mu);
-    for (auto& pr : P.events) {
-        hipEventSynchronize(pr.second);
-        P.pool.push_back(pr.first);
-        P.pool.push_back(pr.second);
+    for (auto& r : P.recs) {
+        hipEventSynchronize(r.e1);
+        P.pool.push_back(r.e0);
+        P.pool.push_back(r.e1);
     }
-    P.events.clear();
+    P.recs.clear();
     P.on = on != 0;
-    P.launches = P.edge_tasks = P.bytes = 0;
-    P.ms = 0.0;
+    for (int k = 0; k < kKinds; ++k) {
+        P.launches[k] = P.tasks[k] = P.bytes[k] = 0;
+        P.ms[k] = 0.0;
+    }
     return KTRUSS_OK;
 }
 
-int32_t ktruss_profile_read(int64_t* launches, double* total_ms, int64_t* edge_tasks, int64_t* bytes) {
+int32_t ktruss_profile_read(int32_t kind, int64_t* launches, double* total_ms, int64_t* tasks, int64_t* bytes) {
     clear_error();
+    if (kind < 0 || kind >= kKinds) return fail(KTRUSS_E_INVALID, "profile kind must be 0..%d", kKinds - 1);
     Profile& P = prof();
     std::lock_guard<std::mutex> lk(P.mu);
-    for (auto& pr : P.events) {
+    for (auto& r : P.recs) {
         float ms = 0.f;
-        hipError_t e = hipEventSynchronize(pr.second);
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, pr.first, pr.second);
+        hipError_t e = hipEventSynchronize(r.e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.e0, r.e1);
         if (e != hipSuccess) return fail_hip(e, "profile event read");
-        P.ms += ms;
-        P.pool.push_back(pr.first);
-        P.pool.push_back(pr.second);
+        P.ms[r.kind] += ms;
+        P.pool.push_back(r.e0);
+        P.pool.push_back(r.e1);
     }
-    P.events.clear();
-    if (launches) *launches = P.launches;
-    if (total_ms) *total_ms = P.ms;
-    if (edge_tasks) *edge_tasks = P.edge_tasks;
-    if (bytes) *bytes = P.bytes;
+    P.recs.clear();
+    if (launches) *launches = P.launches[kind];
+    if (total_ms) *total_ms = P.ms[kind];
+    if (tasks) *tasks = P.tasks[kind];
+    if (bytes) *bytes = P.bytes[kind];
     return KTRUSS_OK;
 }
 
@@ -273,21 +372,29 @@ int32_t ktruss_support(const ktruss_graph* g, const uint8_t* alive, int32_t* sup
     if (rc != KTRUSS_OK) return rc;
     if (g->m > 0 && !support) return fail(KTRUSS_E_INVALID, "support is null");
     hipStream_t s = (hipStream_t)stream;
-    const Work w = carve(g);
+    Work w = carve(g);
     const int32_t n = g->n, m = (int32_t)g->m;
     rc = validate_on_device(g, w, w.b[0].src, s);
     if (rc != KTRUSS_OK) return rc;
     if (m == 0) return KTRUSS_OK;
-    HIP_TRY(launch_init_run(w.b[0], g->rowptr, g->col, n, m, w.ctl, s), "init");
+    const bool csc = uses_csc(g->schedule);
+    HIP_TRY(launch_init_run(w.b[0], g->rowptr, g->col, n, m, s), "init");
+    if (csc) HIP_TRY(launch_build_csc(w.b[0], w.c[0], n, m, w.sc, s), "in-edge lists");
     HIP_TRY(hipMemsetAsync(support, 0, sizeof(int32_t) * (size_t)m, s), "zero support");
     int p = 0;
+    Ctl h{};
+    h.m_buf[0] = m;
     if (alive) {
-        HIP_TRY(launch_compact(w.b[0], w.b[1], n, 1, 0, alive, w.xscan, w.blockcnt, w.blockoff, w.ctl, 0, m, s),
+        HIP_TRY(launch_compact(w.b[0], w.b[1], csc ? &w.c[0] : nullptr, csc ? &w.c[1] : nullptr, n, 1, 0, alive, w.sc,
+                               w.ctl, 0, m, s),
                 "restrict to alive");
         p = 1;
         HIP_TRY(launch_set_final(w.ctl, 1, s), "final buffer");
     }
-    rc = support_pass(g, w, p, m, s);
+    rc = prepare(g, w, p, m, s);
+    if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
+    if (rc != KTRUSS_OK) return rc;
+    rc = support_pass(g, w, p, h.m_buf[p], h, s);
     if (rc != KTRUSS_OK) return rc;
     HIP_TRY(launch_scatter_out(w.b[0], w.b[1], w.ctl, nullptr, support, m, s), "scatter");
     HIP_TRY(hipStreamSynchronize(s), "support sync");
@@ -314,7 +421,7 @@ int32_t ktruss_run(const ktruss_graph* g, int32_t K, uint8_t* mask, int32_t* sup
     if (K < 2) return fail(KTRUSS_E_INVALID, "K must be >= 2 (got %d)", K);
     if (g->m > 0 && (!mask || !support)) return fail(KTRUSS_E_INVALID, "mask/support is null");
     hipStream_t s = (hipStream_t)stream;
-    const Work w = carve(g);
+    Work w = carve(g);
     const int32_t n = g->n, m = (int32_t)g->m;
     rc = validate_on_device(g, w, w.b[0].src, s);
     if (rc != KTRUSS_OK) return rc;
@@ -322,20 +429,27 @@ int32_t ktruss_run(const ktruss_graph* g, int32_t K, uint8_t* mask, int32_t* sup
         if (rounds) *rounds = 1;
         return KTRUSS_OK;
     }
-    HIP_TRY(launch_init_run(w.b[0], g->rowptr, g->col, n, m, w.ctl, s), "init");
+    const bool csc = uses_csc(g->schedule);
+    HIP_TRY(launch_init_run(w.b[0], g->rowptr, g->col, n, m, s), "init");
+    if (csc) HIP_TRY(launch_build_csc(w.b[0], w.c[0], n, m, w.sc, s), "in-edge lists");
     HIP_TRY(hipMemsetAsync(mask, 0, (size_t)m, s), "zero mask");
     HIP_TRY(hipMemsetAsync(support, 0, sizeof(int32_t) * (size_t)m, s), "zero support");
     int p = 0;
-    int32_t m_hint = m;
     Ctl h{};
+    h.m_buf[0] = m;
+    rc = prepare(g, w, 0, m, s);
+    if (rc == KTRUSS_OK && csc) rc = read_ctl(w, h, s);
+    if (rc != KTRUSS_OK) return rc;
+    int32_t m_hint = m;
     for (;;) {
-        rc = support_pass(g, w, p, m_hint, s);
+        rc = support_pass(g, w, p, m_hint, h, s);
         if (rc != KTRUSS_OK) return rc;
-        HIP_TRY(launch_compact(w.b[p], w.b[1 - p], n, 0, K - 2, nullptr, w.xscan, w.blockcnt, w.blockoff, w.ctl, p,
-                               m_hint, s),
+        HIP_TRY(launch_compact(w.b[p], w.b[1 - p], csc ? &w.c[p] : nullptr, csc ? &w.c[1 - p] : nullptr, n, 0, K - 2,
+                               nullptr, w.sc, w.ctl, p, m_hint, s),
                 "prune launch");
-        HIP_TRY(hipMemcpyAsync(&h, w.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s), "control readback");
-        HIP_TRY(hipStreamSynchronize(s), "round sync");
+        rc = prepare(g, w, 1 - p, m_hint, s);
+        if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
+        if (rc != KTRUSS_OK) return rc;
         if (h.done) break;
         m_hint = h.m_buf[1 - p];
         p ^= 1;

@@ -13,6 +13,17 @@ constexpr int kBlock = 256;          // threads per workgroup of the streaming k
 constexpr int kMaxScanBlocks = 4096; // workgroups of the compaction grid (one scan workgroup covers them)
 constexpr int kScanThreads = 1024;
 
+// workgroup-per-hub-row kernel
+constexpr int kHubThreads = 256;     // 4 waves
+constexpr int kHubChunk = 256;       // tasks (in-edges of one row kappa) per hub item
+constexpr int kSpanCap = 32768;      // widest label span staged as a rank bitmap
+constexpr int kSpanWords = kSpanCap / 32;
+constexpr int kKeyCap = 2 * kSpanWords;  // longest row kappa staged in LDS (keys / accumulators)
+
+// static degree heuristic defaults
+constexpr int kDefaultHubMinIn = 8;    // in-edges for a row kappa to be a hub row
+constexpr int kDefaultWaveMin = 192;   // merge length for wavefront-per-edge
+
 // Device-resident control block of one run.  Buffer b of the double-buffered
 // working graph holds m_buf[b] alive edges.
 struct Ctl {
@@ -22,6 +33,9 @@ struct Ctl {
     int32_t rounds;      // support passes executed
     int32_t err;         // validation error bits
     int32_t kept;        // survivors of the last prune
+    int32_t n_items;     // hub items of the current pass
+    int32_t n_wave;      // wavefront-per-edge tasks of the current pass
+    int32_t n_thread;    // thread-per-edge tasks of the current pass
     int32_t pad;
     int64_t removed_total;
 };
@@ -37,14 +51,41 @@ struct Buf {
     int32_t* rowptr;
 };
 
+// In-edge lists of a buffer: for every row kappa, the positions of the edges
+// whose column is kappa (edge[ptr[kappa] .. ptr[kappa+1])).
+struct Csc {
+    int32_t* edge;
+    int32_t* ptr;
+};
+
+// Per-run scratch arrays inside the workspace.
+struct Scratch {
+    int32_t* xscan;       // int32[m+1]: new CSR position of every old position
+    int32_t* cxscan;      // int32[m+1]: same for in-edge list entries
+    int32_t* blockcnt;    // int32[kMaxScanBlocks]
+    int32_t* blockoff;    // int32[kMaxScanBlocks]
+    int32_t* blockcnt2;   // int32[2*kMaxScanBlocks]
+    int32_t* blockoff2;   // int32[2*kMaxScanBlocks]
+    int32_t* tmp_n;       // int32[n]
+    int32_t* itemoff;     // int32[n+1]
+    int32_t* item_kappa;  // int32[item capacity]
+    int32_t* item_c0;     // int32[item capacity]
+    uint8_t* is_hub;      // uint8[n]
+    int32_t* wave_tasks;  // int32[m]
+    int32_t* thread_tasks;// int32[m]
+};
+
 struct Layout {
     size_t col[2], src[2], eid[2], S[2], rowptr[2];
-    size_t xscan;      // int32[m+1]: new position of every old position
-    size_t blockcnt;   // int32[kMaxScanBlocks]
-    size_t blockoff;   // int32[kMaxScanBlocks]
+    size_t cedge[2], cptr[2];
+    size_t xscan, cxscan, blockcnt, blockoff, blockcnt2, blockoff2, tmp_n, itemoff, item_kappa, item_c0, is_hub,
+        wave_tasks, thread_tasks;
     size_t ctl;        // Ctl
     size_t total;
 };
+
+// Upper bound on hub items: one per row plus one per kHubChunk edges.
+inline int64_t item_capacity(int32_t n, int64_t m) { return (int64_t)n + m / kHubChunk + 1; }
 
 Layout layout(int32_t n, int64_t m);
 

@@ -1,0 +1,203 @@
+// Prune + compaction between support passes.
+//
+// The alive edge tasks of buffer p are filtered, order-preserving, into buffer
+// 1-p: a keep flag per element, a per-workgroup count, one workgroup scanning
+// the counts, then a scatter whose positions come from a wave ballot + mbcnt
+// prefix and the wave totals.  Every old position's new position is recorded
+// (xscan) so that row pointers, and the in-edge lists that point at edge
+// positions, can be remapped without another search.
+#include "device_util.h"
+#include "kernels.h"
+
+namespace kt {
+
+namespace {
+
+// ---- keep predicates and emitters
+
+// CSR element e of buffer x; keep = S[e] >= thr (a prune round).
+struct CsrRound {
+    Buf x, y;
+    int32_t thr;
+    __device__ bool keep(int32_t e) const { return x.S[e] >= thr; }
+    __device__ void emit(int32_t e, int32_t q) const {
+        y.col[q] = x.col[e];
+        y.src[q] = x.src[e];
+        y.eid[q] = x.eid[e];
+        y.S[q] = 0;
+    }
+};
+
+// CSR element e; keep = the caller's alive flag of its canonical edge.
+struct CsrAlive {
+    Buf x, y;
+    const uint8_t* alive_can;
+    __device__ bool keep(int32_t e) const { return alive_can[x.eid[e]] != 0; }
+    __device__ void emit(int32_t e, int32_t q) const {
+        y.col[q] = x.col[e];
+        y.src[q] = x.src[e];
+        y.eid[q] = x.eid[e];
+        y.S[q] = 0;
+    }
+};
+
+// In-edge list entry c (an edge position of buffer x); it survives with its
+// edge and is rewritten to that edge's new position.
+template <int MODE>
+struct CscEntry {
+    Buf x;
+    Csc cx, cy;
+    int32_t thr;
+    const uint8_t* alive_can;
+    const int32_t* xscan;  // new CSR positions
+    __device__ bool keep(int32_t c) const {
+        const int32_t e = cx.edge[c];
+        if (MODE == 0) return x.S[e] >= thr;
+        return alive_can[x.eid[e]] != 0;
+    }
+    __device__ void emit(int32_t c, int32_t q) const { cy.edge[q] = xscan[cx.edge[c]]; }
+};
+
+// ---- generic stable filter
+
+__device__ __forceinline__ void chunk_of(int32_t N, int32_t& lo, int32_t& hi) {
+    const int32_t G = (int32_t)gridDim.x;
+    const int32_t chunk = (int32_t)(((int64_t)N + G - 1) / G);
+    lo = (int32_t)min((int64_t)blockIdx.x * chunk, (int64_t)N);
+    hi = (int32_t)min((int64_t)lo + chunk, (int64_t)N);
+}
+
+template <class P>
+__global__ __launch_bounds__(kBlock) void k_filter_count(P pol, const Ctl* __restrict__ ctl, int p, int round,
+                                                       int32_t* __restrict__ blockcnt) {
+    __shared__ int s_wave[kBlock / 64];
+    if (round && ctl->done) return;
+    int32_t lo, hi;
+    chunk_of(ctl->m_buf[p], lo, hi);
+    int c = 0;
+    for (int32_t i = lo + (int32_t)threadIdx.x; i < hi; i += kBlock) c += pol.keep(i);
+    c = block_sum<kBlock>(c, s_wave);
+    if (threadIdx.x == 0) blockcnt[blockIdx.x] = c;
+}
+
+// update: 0 = only the scan; 1 = prune-round bookkeeping (pass count,
+// fixpoint flag, survivor count); 2 = set the survivor count of buffer 1-p.
+__global__ __launch_bounds__(kScanThreads) void k_filter_scan(const int32_t* __restrict__ blockcnt,
+                                                            int32_t* __restrict__ blockoff, int32_t G, Ctl* ctl,
+                                                            int p, int update, int round,
+                                                            int32_t* __restrict__ xscan) {
+    __shared__ int s_wave[kScanThreads / 64];
+    if (round && ctl->done) return;
+    constexpr int PER = kMaxScanBlocks / kScanThreads;
+    const int t = threadIdx.x;
+    int v[PER];
+    int local = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int idx = t * PER + j;
+        v[j] = idx < G ? blockcnt[idx] : 0;
+        local += v[j];
+    }
+    int total;
+    int run = block_excl_sum<kScanThreads>(local, s_wave, total);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int idx = t * PER + j;
+        if (idx < G) blockoff[idx] = run;
+        run += v[j];
+    }
+    if (t == 0) {
+        const int32_t N = ctl->m_buf[p];
+        xscan[N] = total;
+        if (update == 1) {
+            ctl->rounds += 1;
+            const int32_t removed = N - total;
+            ctl->kept = total;
+            if (removed == 0) {
+                ctl->done = 1;
+                ctl->final_buf = p;
+            } else {
+                ctl->m_buf[1 - p] = total;
+                ctl->removed_total += removed;
+            }
+        } else if (update == 2) {
+            ctl->kept = total;
+            ctl->m_buf[1 - p] = total;
+        }
+    }
+}
+
+template <class P>
+__global__ __launch_bounds__(kBlock) void k_filter_scatter(P pol, const Ctl* __restrict__ ctl, int p, int round,
+                                                         const int32_t* __restrict__ blockoff,
+                                                         int32_t* __restrict__ xscan) {
+    __shared__ int s_wave[kBlock / 64];
+    if (round && ctl->done) return;
+    int32_t lo, hi;
+    chunk_of(ctl->m_buf[p], lo, hi);
+    int32_t base = blockoff[blockIdx.x];
+    for (int32_t t0 = lo; t0 < hi; t0 += kBlock) {
+        const int32_t i = t0 + (int32_t)threadIdx.x;
+        const bool in = i < hi;
+        const bool k = in && pol.keep(i);
+        int tot;
+        const int32_t q = base + block_excl_flag<kBlock>(k, s_wave, tot);
+        if (in) {
+            xscan[i] = q;
+            if (k) pol.emit(i, q);
+        }
+        base += tot;
+    }
+}
+
+// new_ptr[s] = xscan[old_ptr[s]] for s in [0, n]
+__global__ __launch_bounds__(kBlock) void k_ptr_remap(const int32_t* __restrict__ old_ptr, int32_t* __restrict__ new_ptr,
+                                                    int32_t n, const int32_t* __restrict__ xscan,
+                                                    const Ctl* __restrict__ ctl, int round) {
+    if (round && ctl->done) return;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s > n) return;
+    new_ptr[s] = xscan[old_ptr[s]];
+}
+
+int32_t filter_grid(int32_t m_hint) {
+    int64_t g = ((int64_t)m_hint + 8 * kBlock - 1) / (8 * kBlock);
+    if (g < 1) g = 1;
+    if (g > kMaxScanBlocks) g = kMaxScanBlocks;
+    return (int32_t)g;
+}
+
+template <class P>
+void run_filter(const P& pol, Ctl* ctl, int p, int update, int round, int32_t* blockcnt, int32_t* blockoff,
+                int32_t* xscan, int32_t m_hint, hipStream_t s) {
+    const int32_t G = filter_grid(m_hint);
+    k_filter_count<P><<<G, kBlock, 0, s>>>(pol, ctl, p, round, blockcnt);
+    k_filter_scan<<<1, kScanThreads, 0, s>>>(blockcnt, blockoff, G, ctl, p, update, round, xscan);
+    k_filter_scatter<P><<<G, kBlock, 0, s>>>(pol, ctl, p, round, blockoff, xscan);
+}
+
+}  // namespace
+
+hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* cy, int32_t n, int mode, int32_t thr,
+                          const uint8_t* alive_can, Scratch& sc, Ctl* ctl, int p, int32_t m_hint, hipStream_t s) {
+    const int round = mode == 0;
+    if (mode == 0) {
+        run_filter(CsrRound{x, y, thr}, ctl, p, 1, 1, sc.blockcnt, sc.blockoff, sc.xscan, m_hint, s);
+    } else {
+        run_filter(CsrAlive{x, y, alive_can}, ctl, p, 2, 0, sc.blockcnt, sc.blockoff, sc.xscan, m_hint, s);
+    }
+    k_ptr_remap<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(x.rowptr, y.rowptr, n, sc.xscan, ctl, round);
+    if (cx && cy) {
+        if (mode == 0) {
+            run_filter(CscEntry<0>{x, *cx, *cy, thr, nullptr, sc.xscan}, ctl, p, 0, 1, sc.blockcnt, sc.blockoff,
+                       sc.cxscan, m_hint, s);
+        } else {
+            run_filter(CscEntry<1>{x, *cx, *cy, 0, alive_can, sc.xscan}, ctl, p, 0, 0, sc.blockcnt, sc.blockoff,
+                       sc.cxscan, m_hint, s);
+        }
+        k_ptr_remap<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(cx->ptr, cy->ptr, n, sc.cxscan, ctl, round);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace kt

@@ -1,32 +1,45 @@
-// Launch wrappers of the device kernels (kernels.hip).  All are asynchronous on
-// `s` and return the hipError_t of the launch.
+// Launch wrappers of the device kernels.  All are asynchronous on `s` and
+// return the hipError_t of the launch.
 #pragma once
 
 #include "common.h"
 
 namespace kt {
 
-// ---- input validation and set-up
-hipError_t launch_validate(const int32_t* rowptr, const int32_t* col, int32_t n, int32_t m,
-                           int32_t* src_out, Ctl* ctl, hipStream_t s);
-hipError_t launch_init_run(const Buf& b, const int32_t* rowptr, const int32_t* col, int32_t n, int32_t m,
+// ---- input validation and set-up (k_setup.hip)
+hipError_t launch_validate(const int32_t* rowptr, const int32_t* col, int32_t n, int32_t m, int32_t* src_out,
                            Ctl* ctl, hipStream_t s);
-
-// ---- one support pass over buffer p (S of that buffer must be zero)
-hipError_t launch_support_thread_edge(const Buf& x, const Ctl* ctl, int p, int32_t m_hint, hipStream_t s);
-
-// ---- prune + compaction of buffer p into buffer 1-p
-// mode 0: keep = S[e] >= thr (a prune round); mode 1: keep = alive_can[eid[e]] != 0
-// (initial restriction to a caller's alive set; never ends the run).
-hipError_t launch_compact(const Buf& x, const Buf& y, int32_t n, int mode, int32_t thr,
-                          const uint8_t* alive_can, int32_t* xscan, int32_t* blockcnt, int32_t* blockoff,
-                          Ctl* ctl, int p, int32_t m_hint, hipStream_t s);
-
-// ---- outputs
+hipError_t launch_init_run(const Buf& b, const int32_t* rowptr, const int32_t* col, int32_t n, int32_t m,
+                           hipStream_t s);
 hipError_t launch_set_final(Ctl* ctl, int f, hipStream_t s);
 hipError_t launch_scatter_out(const Buf& b0, const Buf& b1, const Ctl* ctl, uint8_t* mask, int32_t* support,
                               int32_t m_hint, hipStream_t s);
 hipError_t launch_prune_canonical(const int32_t* support, uint8_t* alive, int32_t m, int32_t thr,
                                   unsigned long long* removed, hipStream_t s);
+
+// ---- prune + compaction of buffer p into buffer 1-p (k_compact.hip)
+// mode 0: keep = S[e] >= thr (a prune round: updates the pass count and the
+// fixpoint flag); mode 1: keep = alive_can[eid[e]] != 0 (restriction to a
+// caller's alive set).  The in-edge lists are compacted too when cx, cy are
+// given.
+hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* cy, int32_t n, int mode, int32_t thr,
+                          const uint8_t* alive_can, Scratch& sc, Ctl* ctl, int p, int32_t m_hint, hipStream_t s);
+
+// ---- scheduling structures (k_sched.hip)
+hipError_t launch_build_csc(const Buf& b, const Csc& c, int32_t n, int32_t m, Scratch& sc, hipStream_t s);
+// Work lists of one support pass over buffer p: hub items (all rows with
+// work under FORCE_HUB; the hub rows of the heuristic or of `learned_hub`
+// otherwise) and, except under FORCE_HUB, the wavefront / thread task lists.
+hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched, const ktruss_tuning& t,
+                               const uint8_t* learned_hub, Scratch& sc, Ctl* ctl, int p, int32_t m_hint,
+                               hipStream_t s);
+
+// ---- support kernels (k_support.hip); count_dev points at the task count
+hipError_t launch_support_thread(const Buf& x, const int32_t* tasks, const int32_t* count_dev, int32_t n_hint,
+                                 const Ctl* ctl, hipStream_t s);
+hipError_t launch_support_wave(const Buf& x, const int32_t* tasks, const int32_t* count_dev, int32_t n_hint,
+                               const Ctl* ctl, hipStream_t s);
+hipError_t launch_support_hub(const Buf& x, const Csc& c, const int32_t* item_kappa, const int32_t* item_c0,
+                              int32_t n_items_hint, const Ctl* ctl, hipStream_t s);
 
 }  // namespace kt

@@ -67,7 +67,7 @@ def load():
         "ktruss_run": ([G, i32, p, p, p, p], i32),
         "ktruss_set_schedule": ([G, i32, p, ctypes.POINTER(ktruss_tuning)], i32),
         "ktruss_profile_enable": ([i32], i32),
-        "ktruss_profile_read": ([p, p, p, p], i32),
+        "ktruss_profile_read": ([i32, p, p, p, p], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -185,11 +185,14 @@ def ktruss_profile_enable(on: bool = True):
     _check(load().ktruss_profile_enable(1 if on else 0))
 
 
-def ktruss_profile_read():
-    """(launches, total_ms, edge_tasks, compulsory_bytes) of the timed support launches."""
+PROFILE_PASS, PROFILE_THREAD, PROFILE_WAVE, PROFILE_HUB = 0, 1, 2, 3
+
+
+def ktruss_profile_read(kind: int = PROFILE_PASS):
+    """(launches, total_ms, tasks, compulsory_bytes) of the timed support launches of `kind`."""
     launches, edges, nbytes = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     ms = ctypes.c_double()
-    _check(load().ktruss_profile_read(ctypes.byref(launches), ctypes.byref(ms), ctypes.byref(edges),
+    _check(load().ktruss_profile_read(kind, ctypes.byref(launches), ctypes.byref(ms), ctypes.byref(edges),
                                       ctypes.byref(nbytes)))
     return launches.value, ms.value, edges.value, nbytes.value
 

@@ -55,17 +55,44 @@ def test_small_graphs(name):
         assert_parity(rp, col, K, label=name)
 
 
+SCHEDULES = [0, 1, 3, 4]   # plain, heuristic, force-wave, force-hub
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("K", [2, 3, 4, 5, 6, 8, 12, 20, 100])
-def test_rmat12(K, rmat12):
+def test_rmat12(K, schedule, rmat12):
     rp, col, _ = build(rmat12)
-    assert_parity(rp, col, K, label="rmat-s12-ef8")
+    assert_parity(rp, col, K, schedule, label="rmat-s12-ef8")
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
+@pytest.mark.parametrize("name", sorted(SMALL))
+def test_small_graphs_schedules(name, schedule):
+    rp, col, _ = build(SMALL[name])
+    for K in (3, 4, 6):
+        assert_parity(rp, col, K, schedule, label=name)
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("seed", [0, 1])
-def test_rmat14_skewed(seed):
+def test_rmat14_skewed(seed, schedule):
     rp, col, _ = build(synth.rmat(14, 16, 0.65, 0.15, 0.15, 40 + seed))
     for K in (3, 5, 9, 16):
-        assert_parity(rp, col, K, label="rmat-s14-ef16-skew%d" % seed)
+        assert_parity(rp, col, K, schedule, label="rmat-s14-ef16-skew%d" % seed)
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_wide_rows_and_spans(schedule):
+    # order=0 keeps ids: rows get long (beyond the LDS key capacity) and label
+    # spans get wide (beyond the bitmap span), exercising the sorted-key and
+    # global-memory lookups of the hub kernel.
+    n, s, d = synth.rmat(15, 16, 0.6, 0.15, 0.15, 91)
+    rp, col, _ = build((n, s, d), order=2)
+    for K in (3, 6):
+        assert_parity(rp, col, K, schedule, label="rmat-s15 descending order")
+    rp, col, _ = build((n, s, d), order=0)
+    for K in (3, 6):
+        assert_parity(rp, col, K, schedule, label="rmat-s15 natural order")
 
 
 @pytest.mark.parametrize("order", [0, 2])
@@ -80,13 +107,16 @@ def test_planted_clique():
     cs, cd = synth.clique_pairs(synth.distinct_vertices(n, 64, 78))
     rp, col, _ = build((n, np.concatenate([s, cs]), np.concatenate([d, cd])))
     for K in (3, 20, 64, 65):
-        assert_parity(rp, col, K, label="rmat13+clique64")
+        for schedule in SCHEDULES:
+            assert_parity(rp, col, K, schedule, label="rmat13+clique64")
 
 
-def test_support_and_prune_calls(rmat12):
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_support_and_prune_calls(schedule, rmat12):
     import torch
     rp, col, _ = build(rmat12)
     g = kt().Graph(rp, col, device="cuda")
+    kt().ktruss_set_schedule(g, schedule)
     print("case ktruss_support all-alive", flush=True)
     sup = kt().ktruss_support(g).cpu().numpy()
     assert np.array_equal(sup, oracle.supports(rp, col))
