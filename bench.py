@@ -57,6 +57,24 @@ def cpu_baseline(workload, Ks, budget_s=30.0):
                       "seed %d): m=%d, %.2f s" % (list(Ks), scale, p["edge_factor"], p["seed"], msub, dt)}
 
 
+def recorded_traffic(workload, schedule):
+    """Per-launch HBM bytes of the support kernel from the rocprofv3 counter runs
+    recorded in profiles/traffic.json (FETCH_SIZE and WRITE_SIZE, scaled by the
+    copy-kernel calibration); None if none was recorded for this workload and
+    schedule, or if the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get("%s/%s" % (workload, schedule))
+    if not rec:
+        return None
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return (rec["fetch_kib_avg"] * rec["fetch_scale"] + rec["write_kib_avg"] * rec["write_scale"]) * 1024.0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -64,9 +82,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="rmat-s20-ef16")
     ap.add_argument("--ks", default=None, help="comma-separated K values (default: the workload's)")
-    ap.add_argument("--schedule", default="plain", choices=["plain", "heuristic", "learned", "wave", "hub"])
+    ap.add_argument("--schedule", default="hub", choices=["plain", "heuristic", "learned", "wave", "hub"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the timed region, copy a device buffer of this size 3 times (a plain copy "
+                         "kernel of known traffic, for scaling hardware byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -142,6 +163,15 @@ def main():
     avg_launch_ms = sup_ms / max(launches, 1)
     achieved = (nbytes / max(launches, 1)) / (avg_launch_ms * 1e-3) / 1e9 if launches else 0.0
 
+    if args.copy_calibration_mib:
+        nel = args.copy_calibration_mib * (1 << 20) // 4
+        a = torch.ones(nel, dtype=torch.int32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -169,7 +199,7 @@ def main():
             "peak": PEAK_HBM_GBPS,
             "unit": "GB/s",
             "frac": achieved / PEAK_HBM_GBPS,
-            "traffic": None,
+            "traffic": recorded_traffic(args.workload, args.schedule),
             "launches": launches,
             "avg_launch_ms": avg_launch_ms,
             "support_share_of_step": sup_ms / (elapsed * 1e3),

@@ -313,7 +313,7 @@ int32_t ktruss_profile_enable(int32_t on) {
     Profile& P = prof();
     std::lock_guard<std::mutex> lk(P.mu);
     for (auto& r : P.recs) {
-        hipEventSynchronize(r.e1);
+        (void)hipEventSynchronize(r.e1);  // only recycles the pair; timings are dropped
         P.pool.push_back(r.e0);
         P.pool.push_back(r.e1);
     }

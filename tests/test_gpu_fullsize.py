@@ -1,0 +1,146 @@
+"""Full-size GPU parity.
+
+* R-MAT scale 20 (15.7M edges), K = 3, 5, 8, 12: the GPU results must equal the
+  oracle's, compared through digests the oracle wrote (tests/golden/digests.json,
+  made by tests/golden/make_digests.py from oracle/ only).
+* R-MAT scale 23 + planted 600-clique (~112M edges), K = 3, 10, 50, 600: the
+  oracle cannot finish this size in a test, so the results are checked through
+  properties that hold at any size: for sampled surviving edges the support
+  equals the triangle count inside the returned truss and is >= K-2; K = 3
+  equals its closed form (survivors = edges in at least one triangle) on sampled
+  edges; the trusses are nested; the planted clique survives K = 600.
+"""
+import hashlib
+import json
+import os
+
+import numpy as np
+import pytest
+
+import synth
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+GOLDEN = json.load(open(os.path.join(HERE, "golden", "digests.json")))
+
+
+def kt():
+    from paper_2009_07929_amd import ktruss
+    return ktruss
+
+
+def digests(rowptr, col, n2o, mask, sup):
+    rows = np.repeat(np.arange(len(rowptr) - 1, dtype=np.int64), np.diff(rowptr))
+    a = n2o[rows].astype(np.int64)
+    b = n2o[col].astype(np.int64)
+    lo, hi = np.minimum(a, b), np.maximum(a, b)
+    keep = mask.astype(bool)
+    order = np.lexsort((hi[keep], lo[keep]))
+    triples = np.stack([lo[keep][order], hi[keep][order], sup[keep][order].astype(np.int64)], axis=1)
+    return {
+        "mask_sha256": hashlib.sha256(np.ascontiguousarray(mask, np.uint8).tobytes()).hexdigest(),
+        "support_sha256": hashlib.sha256(np.ascontiguousarray(sup, "<i4").tobytes()).hexdigest(),
+        "keyed_sha256": hashlib.sha256(np.ascontiguousarray(triples, "<i8").tobytes()).hexdigest(),
+        "truss_edges": int(keep.sum()),
+        "support_sum": int(sup.astype(np.int64).sum()),
+    }
+
+
+@pytest.fixture(scope="module")
+def s20():
+    n, s, d = synth.workload_pairs("rmat-s20-ef16")
+    rp, col, n2o = kt().ktruss_build_csr(s, d, n)
+    return rp, col, n2o
+
+
+@pytest.mark.parametrize("schedule", [0, 1, 4])
+def test_rmat20_digests(schedule, s20):
+    import torch
+    rp, col, n2o = s20
+    gold = GOLDEN["rmat-s20-ef16"]
+    assert gold["m"] == len(col) and gold["n"] == len(rp) - 1
+    g = kt().Graph(rp, col, device="cuda")
+    kt().ktruss_set_schedule(g, schedule)
+    for K in (3, 5, 8, 12):
+        print("case rmat-s20-ef16 K=%d schedule=%d" % (K, schedule), flush=True)
+        mask, sup, rounds = kt().ktruss_run(g, K)
+        torch.cuda.synchronize()
+        got = digests(rp, col, n2o, mask.cpu().numpy(), sup.cpu().numpy())
+        want = GOLDEN["rmat-s20-ef16"]["K"][str(K)]
+        assert rounds == want["rounds"], (K, rounds)
+        for key in ("truss_edges", "support_sum", "mask_sha256", "support_sha256", "keyed_sha256"):
+            assert got[key] == want[key], (K, key)
+
+
+def in_lists(n, col):
+    """Transpose of the upper-triangular CSR: for every vertex, the edge ids whose column it is."""
+    order = np.argsort(col, kind="stable").astype(np.int64)
+    ptr = np.zeros(n + 1, np.int64)
+    np.add.at(ptr, col.astype(np.int64) + 1, 1)
+    return np.cumsum(ptr), order
+
+
+def neighbours(v, rp, col, rows, cptr, cord, keep):
+    out_e = np.arange(rp[v], rp[v + 1])
+    in_e = cord[cptr[v]:cptr[v + 1]]
+    if keep is not None:
+        out_e = out_e[keep[out_e]]
+        in_e = in_e[keep[in_e]]
+    return np.concatenate([col[out_e].astype(np.int64), rows[in_e]])
+
+
+def triangles_of(e, rp, col, rows, cptr, cord, keep=None):
+    a = neighbours(int(rows[e]), rp, col, rows, cptr, cord, keep)
+    b = neighbours(int(col[e]), rp, col, rows, cptr, cord, keep)
+    return len(np.intersect1d(a, b))
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(600)
+def test_rmat23_clique_properties():
+    import torch
+    name = "rmat-s23-ef16-clique600"
+    p = synth.WORKLOADS[name].params
+    n, s, d = synth.workload_pairs(name)
+    clique = synth.distinct_vertices(n, p["clique"], p["clique_seed"])
+    rp, col, n2o = kt().ktruss_build_csr(s, d, n)
+    del s, d
+    m = len(col)
+    print("case %s n=%d m=%d" % (name, n, m), flush=True)
+    g = kt().Graph(rp, col, device="cuda")
+    kt().ktruss_set_schedule(g, 1)
+    rng = np.random.default_rng(2024)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    cptr, cord = in_lists(n, col)
+    o2n = np.empty(n, np.int64)
+    o2n[n2o] = np.arange(n)
+    prev = None
+    for K in (3, 10, 50, 600):
+        print("case %s K=%d" % (name, K), flush=True)
+        mask, sup, rounds = kt().ktruss_run(g, K)
+        torch.cuda.synchronize()
+        mask = mask.cpu().numpy().astype(bool)
+        sup = sup.cpu().numpy()
+        print("  rounds=%d truss=%d" % (rounds, int(mask.sum())), flush=True)
+        assert (sup[~mask] == 0).all()
+        if prev is not None:
+            assert not (mask & ~prev).any()          # T_K lies inside T_K' for K' < K
+        prev = mask
+        alive = np.flatnonzero(mask)
+        for e in (rng.choice(alive, size=min(300, len(alive)), replace=False) if len(alive) else []):
+            c = triangles_of(e, rp, col, rows, cptr, cord, mask)
+            assert c == sup[e] and c >= K - 2, (K, e, c, sup[e])
+        if K == 3:
+            # closed form: the 3-truss keeps exactly the edges in >= 1 triangle, with their round-one supports
+            for e in rng.choice(m, size=300, replace=False):
+                c = triangles_of(e, rp, col, rows, cptr, cord)
+                assert mask[e] == (c >= 1) and (not mask[e] or sup[e] == c), (e, c)
+            assert rounds <= 2
+        if K == 600:
+            cv = np.sort(o2n[clique])
+            keys = set((rows[mask] * n + col[mask]).tolist())
+            for i in range(len(cv)):
+                for j in range(i + 1, len(cv)):
+                    assert int(cv[i] * n + cv[j]) in keys
