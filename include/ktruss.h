@@ -159,6 +159,45 @@ int32_t ktruss_prune(const ktruss_graph* g, int32_t K, const int32_t* support, u
 int32_t ktruss_run(const ktruss_graph* g, int32_t K, uint8_t* mask, int32_t* support,
                    int32_t* rounds, void* stream);
 
+/* ----------------------------------------------------------- batched form */
+/*
+ * Many independent graphs in one fixpoint loop.  The graphs are concatenated
+ * into one upper-triangular CSR (their disjoint union): graph g owns vertices
+ * [vert_off[g], vert_off[g+1]) and its edges are those of its rows, which must
+ * not leave that range.  Since no triangle spans two graphs, the union's
+ * prune-to-fixpoint (Algorithm 1), with every edge tested against its own
+ * graph's K, yields every graph's K-truss.
+ */
+typedef struct ktruss_batch {
+    int32_t G;                 /* graphs */
+    int32_t schedule;          /* KTRUSS_SCHED_* */
+    int64_t n_total;           /* sum of vertex counts (<= INT32_MAX - 1) */
+    int64_t m_total;           /* sum of edge counts (<= INT32_MAX - 1) */
+    const int32_t* vert_off;   /* device, G+1, vert_off[0] = 0, vert_off[G] = n_total, non-decreasing */
+    const int32_t* rowptr;     /* device, n_total+1: the union CSR (edge offsets of graph g: rowptr[vert_off[g]]) */
+    const int32_t* col;        /* device, m_total */
+    void* work;                /* device, >= ktruss_batch_workspace_bytes(G, n_total, m_total, 0) bytes */
+    int64_t work_bytes;
+    ktruss_tuning tuning;
+} ktruss_batch;
+
+/* Workspace bytes of ktruss_run_batched (flags must be 0); negative status on invalid sizes. */
+int64_t ktruss_batch_workspace_bytes(int32_t G, int64_t n_total, int64_t m_total, int32_t flags);
+
+/*
+ * ktruss_run_batched — every graph's K-truss, K per graph.
+ *   K        device int32[G], each >= 2.
+ *   mask     device uint8[m_total] out, support device int32[m_total] out:
+ *            as ktruss_run, indexed by position in the union CSR.
+ *   rounds   device int32[G] out: each graph's pass count (as ktruss_run).
+ * Results equal G separate ktruss_run calls.  Errors: E_INVALID (null
+ * pointers, offsets not covering [0, n_total), an edge between two graphs,
+ * some K < 2, malformed CSR), E_OVERFLOW, E_CAPACITY, E_HIP.  Synchronises
+ * `stream`.
+ */
+int32_t ktruss_run_batched(const ktruss_batch* b, const int32_t* K, uint8_t* mask, int32_t* support,
+                           int32_t* rounds, void* stream);
+
 /*
  * ktruss_set_schedule — selects the support-kernel schedule of g (sets
  * g->schedule, g->mlp_params and, if t is not NULL, g->tuning).  Results do

@@ -35,8 +35,18 @@ void clear_error() {
     t_hip = 0;
 }
 
-Layout layout(int32_t n, int64_t m) {
-    Layout L{};
+namespace {
+
+// Workspace regions (256-byte aligned) for n vertices, m edges and, in the
+// batched form, G graphs.
+struct FullLayout {
+    Layout L;
+    size_t gidv, thrv, graph_done, done_now;
+};
+
+FullLayout full_layout(int32_t n, int64_t m, int32_t G) {
+    FullLayout F{};
+    Layout& L = F.L;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         const size_t o = off;
@@ -69,22 +79,28 @@ Layout layout(int32_t n, int64_t m) {
     L.wave_tasks = take(em);
     L.thread_tasks = take(em);
     L.ctl = take(sizeof(Ctl));
+    if (G > 0) {
+        F.gidv = take(vn);
+        F.thrv = take(vn);
+        F.graph_done = take((size_t)G);
+        F.done_now = take((size_t)G);
+    }
     L.total = off;
-    return L;
+    return F;
 }
-
-namespace {
 
 struct Work {
     Buf b[2];
     Csc c[2];
     Scratch sc;
     Ctl* ctl;
+    BatchCtx batch;  // batch.thrv == nullptr for a single graph
 };
 
-Work carve(const ktruss_graph* g) {
-    const Layout L = layout(g->n, g->m);
-    char* base = (char*)g->work;
+Work carve(void* work, int32_t n, int64_t m, int32_t G) {
+    const FullLayout F = full_layout(n, m, G);
+    const Layout& L = F.L;
+    char* base = (char*)work;
     Work w{};
     for (int b = 0; b < 2; ++b) {
         w.b[b].col = (int32_t*)(base + L.col[b]);
@@ -109,6 +125,12 @@ Work carve(const ktruss_graph* g) {
     w.sc.wave_tasks = (int32_t*)(base + L.wave_tasks);
     w.sc.thread_tasks = (int32_t*)(base + L.thread_tasks);
     w.ctl = (Ctl*)(base + L.ctl);
+    if (G > 0) {
+        w.batch.gidv = (int32_t*)(base + F.gidv);
+        w.batch.thrv = (int32_t*)(base + F.thrv);
+        w.batch.graph_done = (uint8_t*)(base + F.graph_done);
+        w.batch.done_now = (uint8_t*)(base + F.done_now);
+    }
     return w;
 }
 
@@ -118,37 +140,50 @@ int32_t check_sizes(int32_t n, int64_t m) {
     return KTRUSS_OK;
 }
 
-int32_t check_graph(const ktruss_graph* g, bool need_work) {
-    if (!g) return fail(KTRUSS_E_INVALID, "graph is null");
-    const int32_t rc = check_sizes(g->n, g->m);
-    if (rc != KTRUSS_OK) return rc;
-    if (!g->rowptr || (g->m > 0 && !g->col)) return fail(KTRUSS_E_INVALID, "graph rowptr/col is null");
-    if (g->schedule < KTRUSS_SCHED_PLAIN || g->schedule > KTRUSS_SCHED_FORCE_HUB)
-        return fail(KTRUSS_E_INVALID, "unknown schedule %d", g->schedule);
-    if (need_work) {
-        const int64_t need = (int64_t)layout(g->n, g->m).total;
-        if (!g->work) return fail(KTRUSS_E_INVALID, "workspace is null");
-        if (((uintptr_t)g->work & 15u) != 0) return fail(KTRUSS_E_INVALID, "workspace must be 16-byte aligned");
-        if (g->work_bytes < need)
-            return fail(KTRUSS_E_CAPACITY, "workspace has %lld bytes, needs %lld", (long long)g->work_bytes, (long long)need);
-    }
+int32_t check_schedule(int32_t sched) {
+    if (sched < KTRUSS_SCHED_PLAIN || sched > KTRUSS_SCHED_FORCE_HUB)
+        return fail(KTRUSS_E_INVALID, "unknown schedule %d", sched);
     return KTRUSS_OK;
 }
 
-#define HIP_TRY(expr, what)                          \
-    do {                                             \
-        hipError_t e_ = (expr);                      \
+int32_t check_work(const void* work, int64_t work_bytes, int64_t need) {
+    if (!work) return fail(KTRUSS_E_INVALID, "workspace is null");
+    if (((uintptr_t)work & 15u) != 0) return fail(KTRUSS_E_INVALID, "workspace must be 16-byte aligned");
+    if (work_bytes < need)
+        return fail(KTRUSS_E_CAPACITY, "workspace has %lld bytes, needs %lld", (long long)work_bytes, (long long)need);
+    return KTRUSS_OK;
+}
+
+int32_t check_graph(const ktruss_graph* g, bool need_work) {
+    if (!g) return fail(KTRUSS_E_INVALID, "graph is null");
+    int32_t rc = check_sizes(g->n, g->m);
+    if (rc != KTRUSS_OK) return rc;
+    if (!g->rowptr || (g->m > 0 && !g->col)) return fail(KTRUSS_E_INVALID, "graph rowptr/col is null");
+    rc = check_schedule(g->schedule);
+    if (rc != KTRUSS_OK) return rc;
+    if (need_work) return check_work(g->work, g->work_bytes, (int64_t)full_layout(g->n, g->m, 0).L.total);
+    return KTRUSS_OK;
+}
+
+#define HIP_TRY(expr, what)                              \
+    do {                                                 \
+        hipError_t e_ = (expr);                          \
         if (e_ != hipSuccess) return fail_hip(e_, what); \
     } while (0)
 
 // Validates the input CSR on the device (writing each edge's row into
 // src_out) and reads the verdict back.  Synchronises s.
-int32_t validate_on_device(const ktruss_graph* g, const Work& w, int32_t* src_out, hipStream_t s) {
-    HIP_TRY(launch_validate(g->rowptr, g->col, g->n, (int32_t)g->m, src_out, w.ctl, s), "validate launch");
+int32_t validate_on_device(const int32_t* rowptr, const int32_t* col, int32_t n, int32_t m, const Work& w,
+                           int32_t* src_out, hipStream_t s) {
+    HIP_TRY(launch_validate(rowptr, col, n, m, src_out, w.ctl, s), "validate launch");
     int32_t err = 0;
     HIP_TRY(hipMemcpyAsync(&err, &w.ctl->err, sizeof(err), hipMemcpyDeviceToHost, s), "validate readback");
     HIP_TRY(hipStreamSynchronize(s), "validate sync");
-    if (err) return fail(KTRUSS_E_INVALID, "malformed CSR (check bits 0x%x: 1 rowptr range, 2 rowptr[0], 4 rowptr[n]!=m, 8 rowptr not monotone, 16 columns not ascending above the diagonal or >= n)", err);
+    if (err)
+        return fail(KTRUSS_E_INVALID,
+                    "malformed CSR (check bits 0x%x: 1 rowptr range, 2 rowptr[0], 4 rowptr[n]!=m, 8 rowptr not "
+                    "monotone, 16 columns not ascending above the diagonal or >= n)",
+                    err);
     return KTRUSS_OK;
 }
 
@@ -183,14 +218,18 @@ hipEvent_t take_event(Profile& P) {
     return e;
 }
 
-// Event pair around a group of launches, tallied under `kind` when profiling.
+// Event pair around a group of launches, tallied under `kind` when profiling
+// (never while a graph is being captured).
 struct Timer {
     bool on = false;
     int kind = 0;
     hipEvent_t e0 = nullptr, e1 = nullptr;
 };
 
+thread_local bool t_capturing = false;
+
 int32_t timer_begin(Timer& t, int kind, int64_t tasks, int64_t bytes, hipStream_t s) {
+    if (t_capturing) return KTRUSS_OK;
     Profile& P = prof();
     {
         std::lock_guard<std::mutex> lk(P.mu);
@@ -229,33 +268,40 @@ int32_t timed_launch(int kind, int64_t tasks, hipStream_t s, F&& launch) {
 
 bool uses_csc(int sched) { return sched != KTRUSS_SCHED_PLAIN && sched != KTRUSS_SCHED_FORCE_WAVE; }
 
-// One support pass over buffer p.  h holds the host copy of the control
-// block after the pass was prepared (task and item counts).
-int32_t support_pass(const ktruss_graph* g, const Work& w, int p, int32_t m_hint, const Ctl& h, hipStream_t s) {
-    const int sched = g->schedule;
+// Grid sizes of one pass: exact counts in host-loop mode, upper bounds when
+// the pass is captured in a graph (the kernels read the true counts).
+struct PassDims {
+    int32_t m;        // alive edges (upper bound)
+    int32_t items;    // hub items
+    int32_t n_wave;   // wavefront tasks
+    int32_t n_thread; // thread tasks
+};
+
+// One support pass over buffer p.
+int32_t support_pass(int sched, int32_t n, const Work& w, int p, const PassDims& dm, hipStream_t s) {
     const Buf& x = w.b[p];
     Timer tp;
-    int32_t rc = timer_begin(tp, 0, m_hint, 16 * (int64_t)m_hint + 4 * ((int64_t)g->n + 1), s);
+    int32_t rc = timer_begin(tp, 0, dm.m, 16 * (int64_t)dm.m + 4 * ((int64_t)n + 1), s);
     if (rc != KTRUSS_OK) return rc;
     if (sched == KTRUSS_SCHED_PLAIN) {
-        rc = timed_launch(1, m_hint, s, [&] {
-            return launch_support_thread(x, nullptr, &w.ctl->m_buf[p], m_hint, w.ctl, s);
+        rc = timed_launch(1, dm.m, s, [&] {
+            return launch_support_thread(x, nullptr, &w.ctl->m_buf[p], dm.m, w.ctl, s);
         });
     } else if (sched == KTRUSS_SCHED_FORCE_WAVE) {
-        rc = timed_launch(2, m_hint, s, [&] {
-            return launch_support_wave(x, nullptr, &w.ctl->m_buf[p], m_hint, w.ctl, s);
+        rc = timed_launch(2, dm.m, s, [&] {
+            return launch_support_wave(x, nullptr, &w.ctl->m_buf[p], dm.m, w.ctl, s);
         });
     } else {
-        rc = timed_launch(3, h.n_items, s, [&] {
-            return launch_support_hub(x, w.c[p], w.sc.item_kappa, w.sc.item_c0, h.n_items, w.ctl, s);
+        rc = timed_launch(3, dm.items, s, [&] {
+            return launch_support_hub(x, w.c[p], w.sc.item_kappa, w.sc.item_c0, dm.items, w.ctl, s);
         });
         if (rc == KTRUSS_OK && sched != KTRUSS_SCHED_FORCE_HUB) {
-            rc = timed_launch(2, h.n_wave, s, [&] {
-                return launch_support_wave(x, w.sc.wave_tasks, &w.ctl->n_wave, h.n_wave, w.ctl, s);
+            rc = timed_launch(2, dm.n_wave, s, [&] {
+                return launch_support_wave(x, w.sc.wave_tasks, &w.ctl->n_wave, dm.n_wave, w.ctl, s);
             });
             if (rc == KTRUSS_OK)
-                rc = timed_launch(1, h.n_thread, s, [&] {
-                    return launch_support_thread(x, w.sc.thread_tasks, &w.ctl->n_thread, h.n_thread, w.ctl, s);
+                rc = timed_launch(1, dm.n_thread, s, [&] {
+                    return launch_support_thread(x, w.sc.thread_tasks, &w.ctl->n_thread, dm.n_thread, w.ctl, s);
                 });
         }
     }
@@ -269,12 +315,112 @@ int32_t read_ctl(const Work& w, Ctl& h, hipStream_t s) {
     return KTRUSS_OK;
 }
 
-int32_t prepare(const ktruss_graph* g, const Work& w, int p, int32_t m_hint, hipStream_t s) {
-    if (!uses_csc(g->schedule)) return KTRUSS_OK;
-    Scratch sc = w.sc;
-    HIP_TRY(launch_prepare_pass(w.b[p], w.c[p], g->n, g->schedule, g->tuning, nullptr, sc, w.ctl, p, m_hint, s),
+// What one fixpoint run needs besides the workspace.
+struct RunSpec {
+    int32_t n, m;
+    const int32_t* rowptr;
+    const int32_t* col;
+    int sched;
+    ktruss_tuning tuning;
+    int32_t thr;             // K - 2 (single graph)
+    int32_t G;               // graphs (batched form), 0 otherwise
+    const int32_t* K;        // device int32[G] (batched form)
+    int32_t* rounds_dev;     // device int32[G] (batched form)
+};
+
+int32_t prepare(const RunSpec& r, Work& w, int p, int32_t m_hint, hipStream_t s) {
+    if (!uses_csc(r.sched)) return KTRUSS_OK;
+    HIP_TRY(launch_prepare_pass(w.b[p], w.c[p], r.n, r.sched, r.tuning, nullptr, w.sc, w.ctl, p, m_hint, s),
             "prepare pass");
     return KTRUSS_OK;
+}
+
+// Enqueues one prune round reading buffer p: support pass, per-graph status
+// (batched form), prune + compaction into buffer 1-p, preparation of the next
+// pass.  No host interaction: every kernel reads its counts from the control
+// block and does nothing once the fixpoint is reached.
+int32_t enqueue_round(const RunSpec& r, Work& w, int p, const PassDims& dm, hipStream_t s) {
+    int32_t rc = support_pass(r.sched, r.n, w, p, dm, s);
+    if (rc != KTRUSS_OK) return rc;
+    if (r.G > 0) HIP_TRY(launch_batch_status(w.b[p], w.batch, r.G, r.K, r.rounds_dev, w.ctl, s), "batch status");
+    const bool csc = uses_csc(r.sched);
+    HIP_TRY(launch_compact(w.b[p], w.b[1 - p], csc ? &w.c[p] : nullptr, csc ? &w.c[1 - p] : nullptr, r.n, 0, r.thr,
+                           nullptr, w.batch, w.sc, w.ctl, p, dm.m, s),
+            "prune launch");
+    return prepare(r, w, 1 - p, dm.m, s);
+}
+
+// Per-thread private stream for graph capture (default priority).
+hipStream_t capture_stream(hipError_t& e) {
+    thread_local hipStream_t cs = nullptr;
+    e = hipSuccess;
+    if (!cs) e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    return cs;
+}
+
+// Runs rounds from buffer 0 until the fixpoint.  The work before the first
+// round (set-up, in-edge lists, first preparation) is already enqueued on s.
+int32_t run_rounds(const RunSpec& r, Work& w, hipStream_t s, Ctl& h) {
+    int32_t rc;
+    const bool csc = uses_csc(r.sched);
+    h = Ctl{};
+    if (csc) {
+        rc = read_ctl(w, h, s);
+        if (rc != KTRUSS_OK) return rc;
+    } else {
+        h.m_buf[0] = r.m;
+    }
+    const int rps = r.tuning.rounds_per_sync;
+    int p = 0;
+    int32_t m_hint = r.m;
+    if (rps <= 1) {
+        for (;;) {
+            const PassDims dm{m_hint, h.n_items, h.n_wave, h.n_thread};
+            rc = enqueue_round(r, w, p, dm, s);
+            if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
+            if (rc != KTRUSS_OK) return rc;
+            if (h.done) return KTRUSS_OK;
+            m_hint = h.m_buf[1 - p];
+            p ^= 1;
+        }
+    }
+    // hipGraph mode: two rounds (0 -> 1 -> 0) captured once with upper-bound
+    // grids, replayed ceil(rps / 2) times between host checks.
+    hipError_t e;
+    hipStream_t cs = capture_stream(e);
+    if (e != hipSuccess) return fail_hip(e, "capture stream");
+    const PassDims dm{m_hint, kHubMaxGrid, m_hint, m_hint};
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+    t_capturing = true;
+    rc = enqueue_round(r, w, 0, dm, cs);
+    if (rc == KTRUSS_OK) rc = enqueue_round(r, w, 1, dm, cs);
+    t_capturing = false;
+    hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (rc != KTRUSS_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (ec != hipSuccess) return fail_hip(ec, "end capture");
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail_hip(e, "graph instantiate");
+    }
+    const int replays = (rps + 1) / 2;
+    rc = KTRUSS_OK;
+    for (;;) {
+        for (int i = 0; i < replays && rc == KTRUSS_OK; ++i) {
+            e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) rc = fail_hip(e, "graph launch");
+        }
+        if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
+        if (rc != KTRUSS_OK || h.done) break;
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return rc;
 }
 
 }  // namespace
@@ -298,14 +444,24 @@ const char* ktruss_strerror(int32_t code) {
 
 const char* ktruss_last_error_message(void) { return t_msg; }
 int32_t ktruss_last_hip_error(void) { return t_hip; }
-int32_t ktruss_version(void) { return 100; }
+int32_t ktruss_version(void) { return 200; }
 
 int64_t ktruss_workspace_bytes(int32_t n, int64_t m, int32_t flags) {
     clear_error();
     if (flags != 0) return fail(KTRUSS_E_INVALID, "flags must be 0");
     const int32_t rc = check_sizes(n, m);
     if (rc != KTRUSS_OK) return rc;
-    return (int64_t)layout(n, m).total;
+    return (int64_t)full_layout(n, m, 0).L.total;
+}
+
+int64_t ktruss_batch_workspace_bytes(int32_t G, int64_t n_total, int64_t m_total, int32_t flags) {
+    clear_error();
+    if (flags != 0) return fail(KTRUSS_E_INVALID, "flags must be 0");
+    if (G < 0 || n_total < 0) return fail(KTRUSS_E_INVALID, "G and n_total must be >= 0");
+    if (n_total > INT32_MAX - 1) return fail(KTRUSS_E_OVERFLOW, "n_total above INT32_MAX - 1");
+    const int32_t rc = check_sizes((int32_t)n_total, m_total);
+    if (rc != KTRUSS_OK) return rc;
+    return (int64_t)full_layout((int32_t)n_total, m_total, G).L.total;
 }
 
 int32_t ktruss_profile_enable(int32_t on) {
@@ -351,7 +507,8 @@ int32_t ktruss_profile_read(int32_t kind, int64_t* launches, double* total_ms, i
 int32_t ktruss_set_schedule(ktruss_graph* g, int32_t mode, const float* mlp_params, const ktruss_tuning* t) {
     clear_error();
     if (!g) return fail(KTRUSS_E_INVALID, "graph is null");
-    if (mode < KTRUSS_SCHED_PLAIN || mode > KTRUSS_SCHED_FORCE_HUB) return fail(KTRUSS_E_INVALID, "unknown schedule %d", mode);
+    const int32_t rc = check_schedule(mode);
+    if (rc != KTRUSS_OK) return rc;
     g->schedule = mode;
     g->mlp_params = mlp_params;
     if (t) g->tuning = *t;
@@ -362,8 +519,8 @@ int32_t ktruss_validate(const ktruss_graph* g, void* stream) {
     clear_error();
     int32_t rc = check_graph(g, true);
     if (rc != KTRUSS_OK) return rc;
-    const Work w = carve(g);
-    return validate_on_device(g, w, w.b[0].src, (hipStream_t)stream);
+    Work w = carve(g->work, g->n, g->m, 0);
+    return validate_on_device(g->rowptr, g->col, g->n, (int32_t)g->m, w, w.b[0].src, (hipStream_t)stream);
 }
 
 int32_t ktruss_support(const ktruss_graph* g, const uint8_t* alive, int32_t* support, void* stream) {
@@ -372,9 +529,9 @@ int32_t ktruss_support(const ktruss_graph* g, const uint8_t* alive, int32_t* sup
     if (rc != KTRUSS_OK) return rc;
     if (g->m > 0 && !support) return fail(KTRUSS_E_INVALID, "support is null");
     hipStream_t s = (hipStream_t)stream;
-    Work w = carve(g);
+    Work w = carve(g->work, g->n, g->m, 0);
     const int32_t n = g->n, m = (int32_t)g->m;
-    rc = validate_on_device(g, w, w.b[0].src, s);
+    rc = validate_on_device(g->rowptr, g->col, n, m, w, w.b[0].src, s);
     if (rc != KTRUSS_OK) return rc;
     if (m == 0) return KTRUSS_OK;
     const bool csc = uses_csc(g->schedule);
@@ -382,19 +539,20 @@ int32_t ktruss_support(const ktruss_graph* g, const uint8_t* alive, int32_t* sup
     if (csc) HIP_TRY(launch_build_csc(w.b[0], w.c[0], n, m, w.sc, s), "in-edge lists");
     HIP_TRY(hipMemsetAsync(support, 0, sizeof(int32_t) * (size_t)m, s), "zero support");
     int p = 0;
-    Ctl h{};
-    h.m_buf[0] = m;
     if (alive) {
-        HIP_TRY(launch_compact(w.b[0], w.b[1], csc ? &w.c[0] : nullptr, csc ? &w.c[1] : nullptr, n, 1, 0, alive, w.sc,
-                               w.ctl, 0, m, s),
+        HIP_TRY(launch_compact(w.b[0], w.b[1], csc ? &w.c[0] : nullptr, csc ? &w.c[1] : nullptr, n, 1, 0, alive,
+                               w.batch, w.sc, w.ctl, 0, m, s),
                 "restrict to alive");
         p = 1;
         HIP_TRY(launch_set_final(w.ctl, 1, s), "final buffer");
     }
-    rc = prepare(g, w, p, m, s);
+    RunSpec r{n, m, g->rowptr, g->col, g->schedule, g->tuning, 0, 0, nullptr, nullptr};
+    rc = prepare(r, w, p, m, s);
+    Ctl h{};
     if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
     if (rc != KTRUSS_OK) return rc;
-    rc = support_pass(g, w, p, h.m_buf[p], h, s);
+    const PassDims dm{h.m_buf[p], h.n_items, h.n_wave, h.n_thread};
+    rc = support_pass(g->schedule, n, w, p, dm, s);
     if (rc != KTRUSS_OK) return rc;
     HIP_TRY(launch_scatter_out(w.b[0], w.b[1], w.ctl, nullptr, support, m, s), "scatter");
     HIP_TRY(hipStreamSynchronize(s), "support sync");
@@ -421,9 +579,9 @@ int32_t ktruss_run(const ktruss_graph* g, int32_t K, uint8_t* mask, int32_t* sup
     if (K < 2) return fail(KTRUSS_E_INVALID, "K must be >= 2 (got %d)", K);
     if (g->m > 0 && (!mask || !support)) return fail(KTRUSS_E_INVALID, "mask/support is null");
     hipStream_t s = (hipStream_t)stream;
-    Work w = carve(g);
+    Work w = carve(g->work, g->n, g->m, 0);
     const int32_t n = g->n, m = (int32_t)g->m;
-    rc = validate_on_device(g, w, w.b[0].src, s);
+    rc = validate_on_device(g->rowptr, g->col, n, m, w, w.b[0].src, s);
     if (rc != KTRUSS_OK) return rc;
     if (m == 0) {
         if (rounds) *rounds = 1;
@@ -434,29 +592,66 @@ int32_t ktruss_run(const ktruss_graph* g, int32_t K, uint8_t* mask, int32_t* sup
     if (csc) HIP_TRY(launch_build_csc(w.b[0], w.c[0], n, m, w.sc, s), "in-edge lists");
     HIP_TRY(hipMemsetAsync(mask, 0, (size_t)m, s), "zero mask");
     HIP_TRY(hipMemsetAsync(support, 0, sizeof(int32_t) * (size_t)m, s), "zero support");
-    int p = 0;
-    Ctl h{};
-    h.m_buf[0] = m;
-    rc = prepare(g, w, 0, m, s);
-    if (rc == KTRUSS_OK && csc) rc = read_ctl(w, h, s);
+    RunSpec r{n, m, g->rowptr, g->col, g->schedule, g->tuning, K - 2, 0, nullptr, nullptr};
+    rc = prepare(r, w, 0, m, s);
     if (rc != KTRUSS_OK) return rc;
-    int32_t m_hint = m;
-    for (;;) {
-        rc = support_pass(g, w, p, m_hint, h, s);
-        if (rc != KTRUSS_OK) return rc;
-        HIP_TRY(launch_compact(w.b[p], w.b[1 - p], csc ? &w.c[p] : nullptr, csc ? &w.c[1 - p] : nullptr, n, 0, K - 2,
-                               nullptr, w.sc, w.ctl, p, m_hint, s),
-                "prune launch");
-        rc = prepare(g, w, 1 - p, m_hint, s);
-        if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
-        if (rc != KTRUSS_OK) return rc;
-        if (h.done) break;
-        m_hint = h.m_buf[1 - p];
-        p ^= 1;
-    }
+    Ctl h{};
+    rc = run_rounds(r, w, s, h);
+    if (rc != KTRUSS_OK) return rc;
     HIP_TRY(launch_scatter_out(w.b[0], w.b[1], w.ctl, mask, support, m, s), "scatter");
     HIP_TRY(hipStreamSynchronize(s), "run sync");
     if (rounds) *rounds = h.rounds;
+    return KTRUSS_OK;
+}
+
+int32_t ktruss_run_batched(const ktruss_batch* b, const int32_t* K, uint8_t* mask, int32_t* support,
+                           int32_t* rounds, void* stream) {
+    clear_error();
+    if (!b) return fail(KTRUSS_E_INVALID, "batch is null");
+    if (b->G < 0 || b->n_total < 0 || b->m_total < 0) return fail(KTRUSS_E_INVALID, "negative batch sizes");
+    if (b->n_total > INT32_MAX - 1) return fail(KTRUSS_E_OVERFLOW, "n_total above INT32_MAX - 1");
+    int32_t rc = check_sizes((int32_t)b->n_total, b->m_total);
+    if (rc != KTRUSS_OK) return rc;
+    rc = check_schedule(b->schedule);
+    if (rc != KTRUSS_OK) return rc;
+    if (!b->vert_off || !b->rowptr || (b->m_total > 0 && !b->col)) return fail(KTRUSS_E_INVALID, "batch arrays are null");
+    if (b->G > 0 && (!K || !rounds)) return fail(KTRUSS_E_INVALID, "K/rounds is null");
+    if (b->G == 0 && b->n_total > 0) return fail(KTRUSS_E_INVALID, "vertices but no graphs");
+    if (b->m_total > 0 && (!mask || !support)) return fail(KTRUSS_E_INVALID, "mask/support is null");
+    const int32_t n = (int32_t)b->n_total, m = (int32_t)b->m_total, G = b->G;
+    rc = check_work(b->work, b->work_bytes, (int64_t)full_layout(n, m, G).L.total);
+    if (rc != KTRUSS_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    Work w = carve(b->work, n, m, G);
+    w.batch.vert_off = b->vert_off;
+    w.batch.mask = mask;
+    w.batch.support = support;
+    rc = validate_on_device(b->rowptr, b->col, n, m, w, w.b[0].src, s);
+    if (rc != KTRUSS_OK) return rc;
+    HIP_TRY(launch_batch_setup(w.batch, G, n, K, w.b[0].src, b->col, m, w.ctl, s), "batch set-up");
+    int32_t err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, &w.ctl->err, sizeof(err), hipMemcpyDeviceToHost, s), "batch check readback");
+    HIP_TRY(hipStreamSynchronize(s), "batch check sync");
+    if (err) return fail(KTRUSS_E_INVALID, "malformed batch (check bits 0x%x: 32 vertex offsets or K < 2, 64 edge between graphs)", err);
+    HIP_TRY(launch_batch_reset(w.batch, G, rounds, s), "batch reset");
+    HIP_TRY(launch_init_run(w.b[0], b->rowptr, b->col, n, m, s), "init");
+    if (m == 0) {
+        // every graph is empty: one pass that removes nothing
+        HIP_TRY(launch_batch_status(w.b[0], w.batch, G, K, rounds, w.ctl, s), "batch status");
+        HIP_TRY(hipStreamSynchronize(s), "batch sync");
+        return KTRUSS_OK;
+    }
+    const bool csc = uses_csc(b->schedule);
+    if (csc) HIP_TRY(launch_build_csc(w.b[0], w.c[0], n, m, w.sc, s), "in-edge lists");
+    HIP_TRY(hipMemsetAsync(mask, 0, (size_t)m, s), "zero mask");
+    HIP_TRY(hipMemsetAsync(support, 0, sizeof(int32_t) * (size_t)m, s), "zero support");
+    RunSpec r{n, m, b->rowptr, b->col, b->schedule, b->tuning, 0, G, K, rounds};
+    rc = prepare(r, w, 0, m, s);
+    if (rc != KTRUSS_OK) return rc;
+    Ctl h{};
+    rc = run_rounds(r, w, s, h);
+    if (rc != KTRUSS_OK) return rc;
+    HIP_TRY(hipStreamSynchronize(s), "batch sync");
     return KTRUSS_OK;
 }
 

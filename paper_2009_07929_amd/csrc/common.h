@@ -19,6 +19,8 @@ constexpr int kHubChunk = 256;       // tasks (in-edges of one row kappa) per hu
 constexpr int kSpanCap = 32768;      // widest label span staged as a rank bitmap
 constexpr int kSpanWords = kSpanCap / 32;
 constexpr int kKeyCap = 2 * kSpanWords;  // longest row kappa staged in LDS (keys / accumulators)
+constexpr int kHubMaxGrid = 256 * 8;     // persistent hub grid: 8 workgroups per CU
+constexpr int kStreamMaxGrid = 256 * 16; // grid-stride cap of the thread/wave task kernels
 
 // static degree heuristic defaults
 constexpr int kDefaultHubMinIn = 8;    // in-edges for a row kappa to be a hub row
@@ -36,7 +38,7 @@ struct Ctl {
     int32_t n_items;     // hub items of the current pass
     int32_t n_wave;      // wavefront-per-edge tasks of the current pass
     int32_t n_thread;    // thread-per-edge tasks of the current pass
-    int32_t pad;
+    int32_t item_next;   // next hub item to take (persistent hub kernel)
     int64_t removed_total;
 };
 
@@ -73,6 +75,18 @@ struct Scratch {
     uint8_t* is_hub;      // uint8[n]
     int32_t* wave_tasks;  // int32[m]
     int32_t* thread_tasks;// int32[m]
+};
+
+// Batched form: per-vertex graph id and threshold, per-graph state, outputs.
+// thrv == nullptr means a single graph (the scalar threshold applies).
+struct BatchCtx {
+    const int32_t* vert_off;  // int32[G+1]
+    int32_t* gidv;            // int32[n]: vertex -> graph
+    int32_t* thrv;            // int32[n]: K of the vertex's graph, minus 2
+    uint8_t* graph_done;      // uint8[G]
+    uint8_t* done_now;        // uint8[G]: finished in the current pass
+    uint8_t* mask;            // outputs, canonical positions of the union
+    int32_t* support;
 };
 
 struct Layout {

@@ -15,11 +15,28 @@ namespace {
 
 // ---- keep predicates and emitters
 
-// CSR element e of buffer x; keep = S[e] >= thr (a prune round).
+// Prune-round keep test of edge e of buffer x: S[e] >= K-2, with K the
+// graph's own K in the batched form, where edges of graphs that finished in
+// this pass are not kept but written to the outputs.
+__device__ __forceinline__ bool round_keep(const Buf& x, const BatchCtx& b, int32_t thr, int32_t e) {
+    if (!b.thrv) return x.S[e] >= thr;
+    const int32_t v = x.src[e];
+    if (b.done_now[b.gidv[v]]) return false;
+    return x.S[e] >= b.thrv[v];
+}
+
 struct CsrRound {
     Buf x, y;
     int32_t thr;
-    __device__ bool keep(int32_t e) const { return x.S[e] >= thr; }
+    BatchCtx b;
+    __device__ bool keep(int32_t e) const { return round_keep(x, b, thr, e); }
+    __device__ void drop(int32_t e) const {
+        if (b.thrv && b.done_now[b.gidv[x.src[e]]]) {
+            const int32_t c = x.eid[e];
+            b.mask[c] = 1;
+            b.support[c] = x.S[e];
+        }
+    }
     __device__ void emit(int32_t e, int32_t q) const {
         y.col[q] = x.col[e];
         y.src[q] = x.src[e];
@@ -33,6 +50,7 @@ struct CsrAlive {
     Buf x, y;
     const uint8_t* alive_can;
     __device__ bool keep(int32_t e) const { return alive_can[x.eid[e]] != 0; }
+    __device__ void drop(int32_t) const {}
     __device__ void emit(int32_t e, int32_t q) const {
         y.col[q] = x.col[e];
         y.src[q] = x.src[e];
@@ -50,11 +68,13 @@ struct CscEntry {
     int32_t thr;
     const uint8_t* alive_can;
     const int32_t* xscan;  // new CSR positions
+    BatchCtx b;
     __device__ bool keep(int32_t c) const {
         const int32_t e = cx.edge[c];
-        if (MODE == 0) return x.S[e] >= thr;
+        if (MODE == 0) return round_keep(x, b, thr, e);
         return alive_can[x.eid[e]] != 0;
     }
+    __device__ void drop(int32_t) const {}
     __device__ void emit(int32_t c, int32_t q) const { cy.edge[q] = xscan[cx.edge[c]]; }
 };
 
@@ -81,7 +101,9 @@ __global__ __launch_bounds__(kBlock) void k_filter_count(P pol, const Ctl* __res
 }
 
 // update: 0 = only the scan; 1 = prune-round bookkeeping (pass count,
-// fixpoint flag, survivor count); 2 = set the survivor count of buffer 1-p.
+// fixpoint flag, survivor count); 2 = set the survivor count of buffer 1-p;
+// 3 = batched prune round (pass count, survivor count; the run ends in
+// k_batch_end once nothing is kept).
 __global__ __launch_bounds__(kScanThreads) void k_filter_scan(const int32_t* __restrict__ blockcnt,
                                                             int32_t* __restrict__ blockoff, int32_t G, Ctl* ctl,
                                                             int p, int update, int round,
@@ -120,9 +142,11 @@ __global__ __launch_bounds__(kScanThreads) void k_filter_scan(const int32_t* __r
                 ctl->m_buf[1 - p] = total;
                 ctl->removed_total += removed;
             }
-        } else if (update == 2) {
+        } else if (update == 2 || update == 3) {
+            if (update == 3) ctl->rounds += 1;
             ctl->kept = total;
             ctl->m_buf[1 - p] = total;
+            if (update == 3) ctl->removed_total += N - total;
         }
     }
 }
@@ -145,6 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_scatter(P pol, const Ctl* __r
         if (in) {
             xscan[i] = q;
             if (k) pol.emit(i, q);
+            else pol.drop(i);
         }
         base += tot;
     }
@@ -158,6 +183,14 @@ __global__ __launch_bounds__(kBlock) void k_ptr_remap(const int32_t* __restrict_
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s > n) return;
     new_ptr[s] = xscan[old_ptr[s]];
+}
+
+// Batched form: the run ends after the pass that leaves no edge.
+__global__ void k_batch_end(Ctl* ctl, int p) {
+    if (threadIdx.x == 0 && !ctl->done && ctl->m_buf[1 - p] == 0) {
+        ctl->done = 1;
+        ctl->final_buf = 1 - p;
+    }
 }
 
 int32_t filter_grid(int32_t m_hint) {
@@ -179,24 +212,27 @@ void run_filter(const P& pol, Ctl* ctl, int p, int update, int round, int32_t* b
 }  // namespace
 
 hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* cy, int32_t n, int mode, int32_t thr,
-                          const uint8_t* alive_can, Scratch& sc, Ctl* ctl, int p, int32_t m_hint, hipStream_t s) {
+                          const uint8_t* alive_can, const BatchCtx& b, Scratch& sc, Ctl* ctl, int p, int32_t m_hint,
+                          hipStream_t s) {
     const int round = mode == 0;
+    const bool batch = b.thrv != nullptr;
     if (mode == 0) {
-        run_filter(CsrRound{x, y, thr}, ctl, p, 1, 1, sc.blockcnt, sc.blockoff, sc.xscan, m_hint, s);
+        run_filter(CsrRound{x, y, thr, b}, ctl, p, batch ? 3 : 1, 1, sc.blockcnt, sc.blockoff, sc.xscan, m_hint, s);
     } else {
         run_filter(CsrAlive{x, y, alive_can}, ctl, p, 2, 0, sc.blockcnt, sc.blockoff, sc.xscan, m_hint, s);
     }
     k_ptr_remap<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(x.rowptr, y.rowptr, n, sc.xscan, ctl, round);
     if (cx && cy) {
         if (mode == 0) {
-            run_filter(CscEntry<0>{x, *cx, *cy, thr, nullptr, sc.xscan}, ctl, p, 0, 1, sc.blockcnt, sc.blockoff,
+            run_filter(CscEntry<0>{x, *cx, *cy, thr, nullptr, sc.xscan, b}, ctl, p, 0, 1, sc.blockcnt, sc.blockoff,
                        sc.cxscan, m_hint, s);
         } else {
-            run_filter(CscEntry<1>{x, *cx, *cy, 0, alive_can, sc.xscan}, ctl, p, 0, 0, sc.blockcnt, sc.blockoff,
+            run_filter(CscEntry<1>{x, *cx, *cy, 0, alive_can, sc.xscan, b}, ctl, p, 0, 0, sc.blockcnt, sc.blockoff,
                        sc.cxscan, m_hint, s);
         }
         k_ptr_remap<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(cx->ptr, cy->ptr, n, sc.cxscan, ctl, round);
     }
+    if (batch && mode == 0) k_batch_end<<<1, 64, 0, s>>>(ctl, p);
     return hipGetLastError();
 }
 

@@ -146,6 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_hub_items(HubChunks f, int32_t n, co
                                                     const Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k == 0) const_cast<Ctl*>(ctl)->item_next = 0;
     if (k >= n) return;
     const int32_t nch = f((int32_t)k);
     const int32_t o = itemoff[k];

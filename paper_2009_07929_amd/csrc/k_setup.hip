@@ -18,7 +18,7 @@ __global__ void k_ctl_reset(Ctl* ctl, int32_t m) {
         ctl->n_items = 0;
         ctl->n_wave = 0;
         ctl->n_thread = 0;
-        ctl->pad = 0;
+        ctl->item_next = 0;
         ctl->removed_total = 0;
     }
 }

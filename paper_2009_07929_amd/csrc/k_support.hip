@@ -13,6 +13,9 @@ namespace kt {
 
 namespace {
 
+__device__ __forceinline__ void thread_task(const Buf& x, int32_t e);
+__device__ __forceinline__ void wave_task(const Buf& x, int32_t e);
+
 // ------------------------------------------------------ thread-per-edge
 // One thread per task: a merge of the two ascending lists (the mapping of the
 // paper's Kokkos listing).  `tasks` = null means tasks 0..count-1 are the edge
@@ -21,9 +24,11 @@ __global__ __launch_bounds__(kBlock) void k_support_thread(Buf x, const int32_t*
                                                          const int32_t* __restrict__ count, const Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     const int32_t nt = *count;
-    const int32_t t = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (t >= nt) return;
-    const int32_t e = tasks ? tasks[t] : t;
+    for (int32_t t = (int32_t)(blockIdx.x * kBlock + threadIdx.x); t < nt; t += (int32_t)(gridDim.x * kBlock))
+        thread_task(x, tasks ? tasks[t] : t);
+}
+
+__device__ __forceinline__ void thread_task(const Buf& x, int32_t e) {
     const int32_t* __restrict__ col = x.col;
     const int32_t i = x.src[e];
     const int32_t k = col[e];
@@ -63,10 +68,13 @@ __global__ __launch_bounds__(kBlock) void k_support_wave(Buf x, const int32_t* _
                                                        const int32_t* __restrict__ count, const Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     const int32_t nt = *count;
-    const int32_t wid = (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 6);
-    if (wid >= nt) return;
+    const int32_t nw = (int32_t)(gridDim.x * (kBlock / 64));
+    for (int32_t wid = (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 6); wid < nt; wid += nw)
+        wave_task(x, tasks ? tasks[wid] : wid);
+}
+
+__device__ __forceinline__ void wave_task(const Buf& x, int32_t e) {
     const int lane = __lane_id();
-    const int32_t e = tasks ? tasks[wid] : wid;
     const int32_t* __restrict__ col = x.col;
     const int32_t i = x.src[e];
     const int32_t k = col[e];
@@ -109,99 +117,108 @@ __global__ __launch_bounds__(kBlock) void k_support_wave(Buf x, const int32_t* _
 enum { kModeBitmap = 0, kModeKeys = 1, kModeGlobal = 2 };
 
 __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const int32_t* __restrict__ item_kappa,
-                                                           const int32_t* __restrict__ item_c0,
-                                                           const Ctl* __restrict__ ctl) {
+                                                           const int32_t* __restrict__ item_c0, Ctl* ctl) {
     __shared__ uint2 s_bm[kSpanWords];   // rank bitmap {bits, set bits before this word}; or keys
     __shared__ int32_t s_acc[kKeyCap];
     __shared__ int32_t s_e[kHubChunk];
     __shared__ int32_t s_tl[kHubChunk];
     __shared__ int s_wave[kHubThreads / 64];
+    __shared__ int32_t s_it;
     if (ctl->done) return;
-    const int32_t it = (int32_t)blockIdx.x;
-    if (it >= ctl->n_items) return;
-    const int32_t* __restrict__ col = x.col;
-    const int32_t k = item_kappa[it];
-    const int32_t c0 = item_c0[it];
-    const int32_t c1 = min(c0 + kHubChunk, c.ptr[k + 1]);
-    const int32_t ntask = c1 - c0;
-    const int32_t rs = x.rowptr[k], d = x.rowptr[k + 1] - rs;
-    const int t = threadIdx.x;
-    if (t < ntask) {
-        const int32_t e = c.edge[c0 + t];
-        s_e[t] = e;
-        s_tl[t] = x.rowptr[x.src[e] + 1] - e - 1;
-    }
-    const int32_t last = col[rs + d - 1];
-    const int32_t span = last - k;  // labels of row kappa lie in (k, last]
-    const int mode = d > kKeyCap ? kModeGlobal : (span <= kSpanCap ? kModeBitmap : kModeKeys);
-    int32_t* s_keys = reinterpret_cast<int32_t*>(s_bm);
-    if (mode == kModeBitmap) {
-        const int32_t nw = (span + 31) >> 5;
-        for (int32_t j = t; j < nw; j += kHubThreads) s_bm[j] = make_uint2(0u, 0u);
+    const int32_t n_items = ctl->n_items;
+    // Persistent: workgroups pull items from a device counter.  Items are laid
+    // out by ascending kappa and the heaviest rows carry the largest labels, so
+    // they are taken from the end first (longest work first).
+    for (;;) {
         __syncthreads();
-        for (int32_t q = t; q < d; q += kHubThreads) {
-            const int32_t off = col[rs + q] - k - 1;
-            atomicOr(&s_bm[off >> 5].x, 1u << (off & 31));
-        }
+        if (threadIdx.x == 0) s_it = atomicAdd(&ctl->item_next, 1);
         __syncthreads();
-        const int32_t per = (nw + kHubThreads - 1) / kHubThreads;
-        const int32_t j0 = t * per, j1 = min(j0 + per, nw);
-        int local = 0;
-        for (int32_t j = j0; j < j1; ++j) local += __popc(s_bm[j].x);
-        int tot;
-        int run = block_excl_sum<kHubThreads>(local, s_wave, tot);
-        for (int32_t j = j0; j < j1; ++j) {
-            s_bm[j].y = (uint32_t)run;
-            run += __popc(s_bm[j].x);
+        const int32_t it = n_items - 1 - s_it;
+        if (it < 0) break;
+        const int32_t* __restrict__ col = x.col;
+        const int32_t k = item_kappa[it];
+        const int32_t c0 = item_c0[it];
+        const int32_t c1 = min(c0 + kHubChunk, c.ptr[k + 1]);
+        const int32_t ntask = c1 - c0;
+        const int32_t rs = x.rowptr[k], d = x.rowptr[k + 1] - rs;
+        const int t = threadIdx.x;
+        if (t < ntask) {
+            const int32_t e = c.edge[c0 + t];
+            s_e[t] = e;
+            s_tl[t] = x.rowptr[x.src[e] + 1] - e - 1;
         }
-    } else if (mode == kModeKeys) {
-        for (int32_t q = t; q < d; q += kHubThreads) s_keys[q] = col[rs + q];
-    }
-    if (mode != kModeGlobal)
-        for (int32_t q = t; q < d; q += kHubThreads) s_acc[q] = 0;
-    __syncthreads();
+        const int32_t last = col[rs + d - 1];
+        const int32_t span = last - k;  // labels of row kappa lie in (k, last]
+        const int mode = d > kKeyCap ? kModeGlobal : (span <= kSpanCap ? kModeBitmap : kModeKeys);
+        int32_t* s_keys = reinterpret_cast<int32_t*>(s_bm);
+        if (mode == kModeBitmap) {
+            const int32_t nw = (span + 31) >> 5;
+            for (int32_t j = t; j < nw; j += kHubThreads) s_bm[j] = make_uint2(0u, 0u);
+            __syncthreads();
+            for (int32_t q = t; q < d; q += kHubThreads) {
+                const int32_t off = col[rs + q] - k - 1;
+                atomicOr(&s_bm[off >> 5].x, 1u << (off & 31));
+            }
+            __syncthreads();
+            const int32_t per = (nw + kHubThreads - 1) / kHubThreads;
+            const int32_t j0 = t * per, j1 = min(j0 + per, nw);
+            int local = 0;
+            for (int32_t j = j0; j < j1; ++j) local += __popc(s_bm[j].x);
+            int tot;
+            int run = block_excl_sum<kHubThreads>(local, s_wave, tot);
+            for (int32_t j = j0; j < j1; ++j) {
+                s_bm[j].y = (uint32_t)run;
+                run += __popc(s_bm[j].x);
+            }
+        } else if (mode == kModeKeys) {
+            for (int32_t q = t; q < d; q += kHubThreads) s_keys[q] = col[rs + q];
+        }
+        if (mode != kModeGlobal)
+            for (int32_t q = t; q < d; q += kHubThreads) s_acc[q] = 0;
+        __syncthreads();
 
-    const int wv = t >> 6, lane = t & 63;
-    for (int32_t kk = wv; kk < ntask; kk += kHubThreads / 64) {
-        const int32_t e = s_e[kk], L = s_tl[kk], base = e + 1;
-        int cnt = 0;
-        for (int32_t o = 0; o < L; o += 64) {
-            const bool in = o + lane < L;
-            const int32_t pos = base + o + lane;
-            const int32_t w = in ? col[pos] : INT32_MAX;
-            const bool cand = in && w <= last;
-            if (__ballot(cand) == 0) break;  // ascending tail: the rest lies beyond row kappa
-            if (cand) {
-                int32_t q = -1;
-                if (mode == kModeBitmap) {
-                    const int32_t off = w - k - 1;
-                    const uint2 bw = s_bm[off >> 5];
-                    const uint32_t bit = (uint32_t)off & 31u;
-                    if ((bw.x >> bit) & 1u) q = (int32_t)(bw.y + __popc(bw.x & ((1u << bit) - 1u)));
-                } else if (mode == kModeKeys) {
-                    const int32_t qq = lower_bound_i32(s_keys, d, w);
-                    if (s_keys[qq] == w) q = qq;
-                } else {
-                    const int32_t qq = lower_bound_i32(col + rs, d, w);
-                    if (col[rs + qq] == w) q = qq;
-                }
-                if (q >= 0) {
-                    atomicAdd(&x.S[pos], 1);
-                    if (mode != kModeGlobal) atomicAdd(&s_acc[q], 1);
-                    else atomicAdd(&x.S[rs + q], 1);
-                    ++cnt;
+        const int wv = t >> 6, lane = t & 63;
+        for (int32_t kk = wv; kk < ntask; kk += kHubThreads / 64) {
+            const int32_t e = s_e[kk], L = s_tl[kk], base = e + 1;
+            int cnt = 0;
+            for (int32_t o = 0; o < L; o += 64) {
+                const bool in = o + lane < L;
+                const int32_t pos = base + o + lane;
+                const int32_t w = in ? col[pos] : INT32_MAX;
+                const bool cand = in && w <= last;
+                if (__ballot(cand) == 0) break;  // ascending tail: the rest lies beyond row kappa
+                if (cand) {
+                    int32_t q = -1;
+                    if (mode == kModeBitmap) {
+                        const int32_t off = w - k - 1;
+                        const uint2 bw = s_bm[off >> 5];
+                        const uint32_t bit = (uint32_t)off & 31u;
+                        if ((bw.x >> bit) & 1u) q = (int32_t)(bw.y + __popc(bw.x & ((1u << bit) - 1u)));
+                    } else if (mode == kModeKeys) {
+                        const int32_t qq = lower_bound_i32(s_keys, d, w);
+                        if (s_keys[qq] == w) q = qq;
+                    } else {
+                        const int32_t qq = lower_bound_i32(col + rs, d, w);
+                        if (col[rs + qq] == w) q = qq;
+                    }
+                    if (q >= 0) {
+                        atomicAdd(&x.S[pos], 1);
+                        if (mode != kModeGlobal) atomicAdd(&s_acc[q], 1);
+                        else atomicAdd(&x.S[rs + q], 1);
+                        ++cnt;
+                    }
                 }
             }
+            cnt = wave_sum(cnt);
+            if (lane == 0 && cnt) atomicAdd(&x.S[e], cnt);
         }
-        cnt = wave_sum(cnt);
-        if (lane == 0 && cnt) atomicAdd(&x.S[e], cnt);
+        __syncthreads();
+        if (mode != kModeGlobal)
+            for (int32_t q = t; q < d; q += kHubThreads) {
+                const int32_t a = s_acc[q];
+                if (a) atomicAdd(&x.S[rs + q], a);
+            }
     }
-    __syncthreads();
-    if (mode != kModeGlobal)
-        for (int32_t q = t; q < d; q += kHubThreads) {
-            const int32_t a = s_acc[q];
-            if (a) atomicAdd(&x.S[rs + q], a);
-        }
 }
 
 }  // namespace
@@ -209,21 +226,21 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
 hipError_t launch_support_thread(const Buf& x, const int32_t* tasks, const int32_t* count_dev, int32_t n_hint,
                                  const Ctl* ctl, hipStream_t s) {
     if (n_hint <= 0) return hipSuccess;
-    k_support_thread<<<grid_for(n_hint), kBlock, 0, s>>>(x, tasks, count_dev, ctl);
+    k_support_thread<<<min(grid_for(n_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, tasks, count_dev, ctl);
     return hipGetLastError();
 }
 
 hipError_t launch_support_wave(const Buf& x, const int32_t* tasks, const int32_t* count_dev, int32_t n_hint,
                                const Ctl* ctl, hipStream_t s) {
     if (n_hint <= 0) return hipSuccess;
-    k_support_wave<<<grid_for((int64_t)n_hint * 64), kBlock, 0, s>>>(x, tasks, count_dev, ctl);
+    k_support_wave<<<min(grid_for((int64_t)n_hint * 64), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, tasks, count_dev, ctl);
     return hipGetLastError();
 }
 
 hipError_t launch_support_hub(const Buf& x, const Csc& c, const int32_t* item_kappa, const int32_t* item_c0,
-                              int32_t n_items_hint, const Ctl* ctl, hipStream_t s) {
+                              int32_t n_items_hint, Ctl* ctl, hipStream_t s) {
     if (n_items_hint <= 0) return hipSuccess;
-    k_support_hub<<<n_items_hint, kHubThreads, 0, s>>>(x, c, item_kappa, item_c0, ctl);
+    k_support_hub<<<min(n_items_hint, kHubMaxGrid), kHubThreads, 0, s>>>(x, c, item_kappa, item_c0, ctl);
     return hipGetLastError();
 }
 

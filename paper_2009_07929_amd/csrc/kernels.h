@@ -22,8 +22,19 @@ hipError_t launch_prune_canonical(const int32_t* support, uint8_t* alive, int32_
 // fixpoint flag); mode 1: keep = alive_can[eid[e]] != 0 (restriction to a
 // caller's alive set).  The in-edge lists are compacted too when cx, cy are
 // given.
+// With a batch context (b.thrv set) the threshold is per vertex, edges of
+// graphs finished in this pass are written to the outputs and dropped, and
+// the run ends when no edge is left.
 hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* cy, int32_t n, int mode, int32_t thr,
-                          const uint8_t* alive_can, Scratch& sc, Ctl* ctl, int p, int32_t m_hint, hipStream_t s);
+                          const uint8_t* alive_can, const BatchCtx& b, Scratch& sc, Ctl* ctl, int p, int32_t m_hint,
+                          hipStream_t s);
+
+// ---- batched form (k_batch.hip)
+hipError_t launch_batch_setup(const BatchCtx& b, int32_t G, int32_t n_total, const int32_t* K, const int32_t* src,
+                              const int32_t* col, int32_t m, Ctl* ctl, hipStream_t s);
+hipError_t launch_batch_reset(const BatchCtx& b, int32_t G, int32_t* rounds, hipStream_t s);
+hipError_t launch_batch_status(const Buf& x, const BatchCtx& b, int32_t G, const int32_t* K, int32_t* rounds,
+                               const Ctl* ctl, hipStream_t s);
 
 // ---- scheduling structures (k_sched.hip)
 hipError_t launch_build_csc(const Buf& b, const Csc& c, int32_t n, int32_t m, Scratch& sc, hipStream_t s);
@@ -40,6 +51,6 @@ hipError_t launch_support_thread(const Buf& x, const int32_t* tasks, const int32
 hipError_t launch_support_wave(const Buf& x, const int32_t* tasks, const int32_t* count_dev, int32_t n_hint,
                                const Ctl* ctl, hipStream_t s);
 hipError_t launch_support_hub(const Buf& x, const Csc& c, const int32_t* item_kappa, const int32_t* item_c0,
-                              int32_t n_items_hint, const Ctl* ctl, hipStream_t s);
+                              int32_t n_items_hint, Ctl* ctl, hipStream_t s);
 
 }  // namespace kt

@@ -68,6 +68,8 @@ def load():
         "ktruss_set_schedule": ([G, i32, p, ctypes.POINTER(ktruss_tuning)], i32),
         "ktruss_profile_enable": ([i32], i32),
         "ktruss_profile_read": ([i32, p, p, p, p], i32),
+        "ktruss_batch_workspace_bytes": ([i32, i64, i64, i32], i64),
+        "ktruss_run_batched": ([ctypes.POINTER(ktruss_batch), p, p, p, p, p], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -208,3 +210,90 @@ def ktruss_run(g: Graph, K: int, mask=None, support=None, stream=None):
     _check(load().ktruss_run(ctypes.byref(g.c), K, _ptr(mask), _ptr(support), ctypes.byref(rounds),
                              _stream(stream)))
     return mask[: g.m], support[: g.m], rounds.value
+
+
+# ------------------------------------------------------------------ batched form
+
+class ktruss_batch(ctypes.Structure):
+    _fields_ = [("G", ctypes.c_int32), ("schedule", ctypes.c_int32), ("n_total", ctypes.c_int64),
+                ("m_total", ctypes.c_int64), ("vert_off", ctypes.c_void_p), ("rowptr", ctypes.c_void_p),
+                ("col", ctypes.c_void_p), ("work", ctypes.c_void_p), ("work_bytes", ctypes.c_int64),
+                ("tuning", ktruss_tuning)]
+
+
+def ktruss_batch_workspace_bytes(G: int, n_total: int, m_total: int, flags: int = 0) -> int:
+    r = load().ktruss_batch_workspace_bytes(G, n_total, m_total, flags)
+    if r < 0:
+        _check(int(r))
+    return int(r)
+
+
+def union_csr(graphs):
+    """Concatenate per-graph CSRs [(rowptr, col), ...] into the union CSR.
+
+    Returns (vert_off int32[G+1], rowptr int32[n_total+1], col int32[m_total])."""
+    ns = [len(rp) - 1 for rp, _ in graphs]
+    ms = [len(c) for _, c in graphs]
+    vert_off = np.zeros(len(graphs) + 1, np.int64)
+    vert_off[1:] = np.cumsum(ns)
+    edge_off = np.zeros(len(graphs) + 1, np.int64)
+    edge_off[1:] = np.cumsum(ms)
+    if vert_off[-1] > 2**31 - 2 or edge_off[-1] > 2**31 - 2:
+        raise ValueError("batch too large for int32 offsets")
+    rowptr = np.concatenate([np.asarray(rp[:-1], np.int64) + edge_off[g] for g, (rp, _) in enumerate(graphs)]
+                            + [np.array([edge_off[-1]], np.int64)]).astype(np.int32)
+    col = (np.concatenate([np.asarray(c, np.int64) + vert_off[g] for g, (_, c) in enumerate(graphs)])
+           if edge_off[-1] else np.zeros(0, np.int64)).astype(np.int32)
+    return vert_off.astype(np.int32), rowptr, col
+
+
+class Batch:
+    """Device-resident union CSR of many graphs plus its workspace."""
+
+    def __init__(self, graphs=None, device="cuda", schedule=SCHED_PLAIN, vert_off=None, rowptr=None, col=None):
+        import torch
+        if graphs is not None:
+            vert_off, rowptr, col = union_csr(graphs)
+        self.G = len(vert_off) - 1
+        self.n_total = len(rowptr) - 1
+        self.m_total = len(col)
+        self.vert_off = torch.from_numpy(np.ascontiguousarray(vert_off, np.int32)).to(device)
+        self.rowptr = torch.from_numpy(np.ascontiguousarray(rowptr, np.int32)).to(device)
+        self.col = torch.from_numpy(np.ascontiguousarray(col if len(col) else np.zeros(1), np.int32)).to(device)
+        nbytes = ktruss_batch_workspace_bytes(self.G, self.n_total, self.m_total)
+        self.work = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.c = ktruss_batch()
+        self.c.G = self.G
+        self.c.schedule = schedule
+        self.c.n_total = self.n_total
+        self.c.m_total = self.m_total
+        self.c.vert_off = self.vert_off.data_ptr()
+        self.c.rowptr = self.rowptr.data_ptr()
+        self.c.col = self.col.data_ptr()
+        self.c.work = self.work.data_ptr()
+        self.c.work_bytes = nbytes
+
+    @property
+    def device(self):
+        return self.rowptr.device
+
+    def edge_offsets(self):
+        """Edge offset of every graph in the union CSR (host int64[G+1])."""
+        vo = self.vert_off.cpu().numpy().astype(np.int64)
+        return self.rowptr.cpu().numpy().astype(np.int64)[vo]
+
+
+def ktruss_run_batched(b: Batch, K, mask=None, support=None, rounds=None, stream=None):
+    """Every graph's K-truss (K per graph).  Returns (mask, support, rounds) device tensors."""
+    import torch
+    K = torch.as_tensor(np.ascontiguousarray(K, np.int32) if not isinstance(K, torch.Tensor) else K)
+    K = K.to(device=b.device, dtype=torch.int32).contiguous()
+    if mask is None:
+        mask = torch.empty(max(b.m_total, 1), dtype=torch.uint8, device=b.device)
+    if support is None:
+        support = torch.empty(max(b.m_total, 1), dtype=torch.int32, device=b.device)
+    if rounds is None:
+        rounds = torch.empty(max(b.G, 1), dtype=torch.int32, device=b.device)
+    _check(load().ktruss_run_batched(ctypes.byref(b.c), _ptr(K), _ptr(mask), _ptr(support), _ptr(rounds),
+                                     _stream(stream)))
+    return mask[: b.m_total], support[: b.m_total], rounds[: b.G]
