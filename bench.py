@@ -1,16 +1,23 @@
 """Throughput of the K-truss hot path on one MI355X.
 
-A step is one full prune-to-fixpoint K-truss run (supports, prune, repeat until
-nothing is removed) for every K of the workload's K sweep, on a graph already
+Main workload (default): R-MAT scale 20, edge factor 16 (15.7M edges), K sweep
+3, 5, 8, 12.  A step is one full prune-to-fixpoint K-truss run (supports, prune,
+repeat until nothing is removed) for every K of the sweep, on a graph already
 resident in HBM.  value = edges processed per second = (number of K values x m)
-/ step time, the paper's ME/s definition (input edges over wall time of a
+/ step time: the paper's ME/s definition (input edges over the wall time of a
 complete K-truss), summed over the sweep.
 
-Prints one JSON line (rank 0).  Only one GPU is used; --gpus above 1 exits.
+Extra legs (on by default, --no-extras to skip), reported inside the same line:
+  batched: 4096 Chung-Lu graphs (K per graph) in one batched run, edges/s =
+           sum of edges / batch time, next to the same graphs run one at a time
+           with the plain thread-per-edge kernel and with the main schedule.
+
+Prints one JSON line.  Only one GPU is used; --gpus above 1 exits.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,10 +28,28 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
+SCHEDULES = {"plain": 0, "heuristic": 1, "learned": 2, "wave": 3, "hub": 4}
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
+
+
+def recorded_traffic(workload, schedule):
+    """Per-launch HBM bytes of the support kernel from the rocprofv3 counter runs
+    recorded in profiles/traffic.json (FETCH_SIZE and WRITE_SIZE, scaled by the
+    copy-kernel calibration); None if none was recorded for this workload and
+    schedule, or if the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path)).get("%s/%s" % (workload, schedule))
+    if not rec:
+        return None
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return (rec["fetch_kib_avg"] * rec["fetch_scale"] + rec["write_kib_avg"] * rec["write_scale"]) * 1024.0
 
 
 def cpu_baseline(workload, Ks, budget_s=30.0):
@@ -32,11 +57,10 @@ def cpu_baseline(workload, Ks, budget_s=30.0):
     level-synchronous peel) timed on a bounded sample of the workload: smaller
     instances of the same R-MAT generator (same a, b, c and edge factor), the
     scale raised one step at a time while the whole K sweep stays within about
-    a third of `budget_s`.  edges/s = (len(Ks) x sample edges) / sweep time."""
+    a sixth of `budget_s`.  edges/s = (len(Ks) x sample edges) / sweep time."""
     import oracle
     import synth
-    w = synth.WORKLOADS[workload]
-    p = w.params
+    p = synth.WORKLOADS[workload].params
     if "scale" not in p:
         return None
     a, b, c = p["abc"]
@@ -57,51 +81,15 @@ def cpu_baseline(workload, Ks, budget_s=30.0):
                       "seed %d): m=%d, %.2f s" % (list(Ks), scale, p["edge_factor"], p["seed"], msub, dt)}
 
 
-def recorded_traffic(workload, schedule):
-    """Per-launch HBM bytes of the support kernel from the rocprofv3 counter runs
-    recorded in profiles/traffic.json (FETCH_SIZE and WRITE_SIZE, scaled by the
-    copy-kernel calibration); None if none was recorded for this workload and
-    schedule, or if the kernel source changed since."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
-        return None
-    rec = json.load(open(path)).get("%s/%s" % (workload, schedule))
-    if not rec:
-        return None
-    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
-        return None
-    return (rec["fetch_kib_avg"] * rec["fetch_scale"] + rec["write_kib_avg"] * rec["write_scale"]) * 1024.0
+def tuning(kt, rounds_per_sync):
+    t = kt.ktruss_tuning()
+    t.rounds_per_sync = rounds_per_sync
+    return t
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="rmat-s20-ef16")
-    ap.add_argument("--ks", default=None, help="comma-separated K values (default: the workload's)")
-    ap.add_argument("--schedule", default="hub", choices=["plain", "heuristic", "learned", "wave", "hub"])
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=30.0)
-    ap.add_argument("--copy-calibration-mib", type=int, default=0,
-                    help="after the timed region, copy a device buffer of this size 3 times (a plain copy "
-                         "kernel of known traffic, for scaling hardware byte counters)")
-    args = ap.parse_args()
-
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(each GPU would run its own graphs; see the sharding notes in the design document).",
-              file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
+def single_sweep(args, kt, torch):
+    """The main leg: K sweep on one large graph.  Returns the JSON dict."""
     import synth
-    from paper_2009_07929_amd import ktruss as kt
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     w = synth.WORKLOADS[args.workload]
     Ks = tuple(int(k) for k in args.ks.split(",")) if args.ks else w.Ks
     t0 = time.perf_counter()
@@ -114,20 +102,15 @@ def main():
     m = len(col)
     log("workload %s: n=%d m=%d (gen %.1fs, csr %.1fs)" % (args.workload, n, m, t_gen, t_build))
 
-    sched = {"plain": kt.SCHED_PLAIN, "heuristic": kt.SCHED_HEURISTIC, "learned": kt.SCHED_LEARNED,
-             "wave": kt.SCHED_FORCE_WAVE, "hub": kt.SCHED_FORCE_HUB}[args.schedule]
     g = kt.Graph(rowptr, col, device="cuda:0")
-    kt.ktruss_set_schedule(g, sched)
+    kt.ktruss_set_schedule(g, SCHEDULES[args.schedule], None, tuning(kt, args.rounds_per_sync))
     mask = torch.empty(m, dtype=torch.uint8, device="cuda:0")
     sup = torch.empty(m, dtype=torch.int32, device="cuda:0")
     stream = torch.cuda.current_stream()
 
     def step():
-        rounds = []
         for K in Ks:
-            _, _, r = kt.ktruss_run(g, K, mask, sup, stream)
-            rounds.append(r)
-        return rounds
+            kt.ktruss_run(g, K, mask, sup, stream)
 
     for i in range(args.warmup):
         step()
@@ -140,15 +123,14 @@ def main():
         _, _, r = kt.ktruss_run(g, K, mask, sup, stream)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        per_k[str(K)] = {"rounds": r, "ms": dt * 1e3, "edges_per_s": m / dt,
-                         "truss_edges": int(mask.sum().item())}
+        per_k[str(K)] = {"rounds": r, "ms": dt * 1e3, "edges_per_s": m / dt, "truss_edges": int(mask.sum().item())}
+    # support-pass timing: HIP events on the launch stream, host-loop rounds
+    # (graph-replayed rounds are not bracketed by events)
+    kt.ktruss_set_schedule(g, SCHEDULES[args.schedule], None, tuning(kt, 0))
     kt.ktruss_profile_enable(True)
+    for K in Ks:
+        kt.ktruss_run(g, K, mask, sup, stream)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
     launches, sup_ms, edge_tasks, nbytes = kt.ktruss_profile_read(kt.PROFILE_PASS)
     kinds = {}
     for name, kind in (("thread", kt.PROFILE_THREAD), ("wave", kt.PROFILE_WAVE), ("hub", kt.PROFILE_HUB)):
@@ -156,28 +138,22 @@ def main():
         if nl:
             kinds[name] = {"launches": nl, "ms": ms, "tasks": tasks}
     kt.ktruss_profile_enable(False)
+    kt.ktruss_set_schedule(g, SCHEDULES[args.schedule], None, tuning(kt, args.rounds_per_sync))
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
     log("timed %d steps in %.3fs" % (args.steps, elapsed))
 
     ms_per_step = elapsed * 1e3 / args.steps
     value = len(Ks) * m * args.steps / elapsed
-    avg_launch_ms = sup_ms / max(launches, 1)
-    achieved = (nbytes / max(launches, 1)) / (avg_launch_ms * 1e-3) / 1e9 if launches else 0.0
-
-    if args.copy_calibration_mib:
-        nel = args.copy_calibration_mib * (1 << 20) // 4
-        a = torch.ones(nel, dtype=torch.int32, device="cuda:0")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(args.workload, Ks, args.cpu_budget)
-
-    out = {
+    avg_pass_ms = sup_ms / max(launches, 1)
+    achieved = (nbytes / max(launches, 1)) / (avg_pass_ms * 1e-3) / 1e9 if launches else 0.0
+    del g
+    return {
         "metric": "edges processed/s per K + HBM GB/s; learned/batched vs plain GPU, bit-exact",
         "value": value,
         "unit": "edges/s",
@@ -191,9 +167,9 @@ def main():
         "dtype": "int32",
         "data": "synthetic",
         "config": {"workload": args.workload, "n": n, "m": m, "Ks": list(Ks), "schedule": args.schedule,
-                   "per_K": per_k},
+                   "rounds_per_sync": args.rounds_per_sync, "per_K": per_k},
         "roofline": {
-            "kernel": "support pass",
+            "kernel": "support pass (k_support_hub under the hub schedule)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": PEAK_HBM_GBPS,
@@ -201,12 +177,113 @@ def main():
             "frac": achieved / PEAK_HBM_GBPS,
             "traffic": recorded_traffic(args.workload, args.schedule),
             "launches": launches,
-            "avg_launch_ms": avg_launch_ms,
-            "support_share_of_step": sup_ms / (elapsed * 1e3),
+            "avg_launch_ms": avg_pass_ms,
+            "bytes_per_launch": nbytes / max(launches, 1),
             "variants": kinds,
         },
-        "cpu_baseline": cpu,
     }
+
+
+def batched_leg(args, kt, torch, count):
+    """Batched run of `count` Chung-Lu graphs vs the same graphs one at a time."""
+    import numpy as np
+    import synth
+    t0 = time.perf_counter()
+    gs = synth.batch_graphs(count, 5)
+    Kg = np.array([g[3] for g in gs], np.int32)
+    csr = kt.build_csrs([(n, s, d) for n, s, d, _ in gs])
+    del gs
+    t_prep = time.perf_counter() - t0
+    msum = sum(len(c) for _, c in csr)
+    log("batch: %d graphs, %d edges (prep %.1fs)" % (count, msum, t_prep))
+    b = kt.Batch(csr, device="cuda:0", schedule=SCHEDULES[args.schedule])
+    b.c.tuning = tuning(kt, args.rounds_per_sync)
+    K_d = torch.from_numpy(Kg).cuda()
+    mask = torch.empty(b.m_total, dtype=torch.uint8, device="cuda:0")
+    sup = torch.empty(b.m_total, dtype=torch.int32, device="cuda:0")
+    rounds = torch.empty(b.G, dtype=torch.int32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    kt.ktruss_run_batched(b, K_d, mask, sup, rounds, stream)      # warm-up
+    torch.cuda.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        kt.ktruss_run_batched(b, K_d, mask, sup, rounds, stream)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    batch_rounds = rounds.cpu().numpy()
+    out = {"workload": "chunglu-batch-%d" % count, "graphs": count, "edges": msum,
+           "batched_edges_per_s": msum / t_batch, "batched_ms": t_batch * 1e3,
+           "max_rounds": int(batch_rounds.max()), "schedule": args.schedule}
+    del b, mask, sup
+    # the same graphs one at a time (graph and output buffers resident before timing)
+    for name in ("plain", args.schedule):
+        graphs = [kt.Graph(rp, c, device="cuda:0", schedule=SCHEDULES[name]) for rp, c in csr]
+        outs = [(torch.empty(max(len(c), 1), dtype=torch.uint8, device="cuda:0"),
+                 torch.empty(max(len(c), 1), dtype=torch.int32, device="cuda:0")) for _, c in csr]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        agree = True
+        for i, g in enumerate(graphs):
+            _, _, r = kt.ktruss_run(g, int(Kg[i]), outs[i][0], outs[i][1], stream)
+            agree &= r == int(batch_rounds[i])
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t0
+        out["per_graph_%s_edges_per_s" % name] = msum / t_seq
+        out["per_graph_%s_ms" % name] = t_seq * 1e3
+        out["rounds_agree_%s" % name] = bool(agree)
+        del graphs, outs
+    out["batched_vs_plain"] = out["batched_edges_per_s"] / out["per_graph_plain_edges_per_s"]
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="rmat-s20-ef16")
+    ap.add_argument("--ks", default=None, help="comma-separated K values (default: the workload's)")
+    ap.add_argument("--schedule", default="hub", choices=sorted(SCHEDULES))
+    ap.add_argument("--rounds-per-sync", type=int, default=0,
+                    help="prune rounds replayed from a hipGraph per host check (<= 1: host loop)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=30.0)
+    ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the timed region, copy a device buffer of this size 3 times (a plain copy "
+                         "kernel of known traffic, for scaling hardware byte counters)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(each GPU would run its own graphs; see the sharding notes in the design document).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2009_07929_amd import ktruss as kt
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    out = single_sweep(args, kt, torch)
+
+    if args.copy_calibration_mib:
+        nel = args.copy_calibration_mib * (1 << 20) // 4
+        a = torch.ones(nel, dtype=torch.int32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    if not args.no_extras:
+        log("batched leg ...")
+        out["batched"] = batched_leg(args, kt, torch, args.batch_graphs)
+    out["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(args.workload, tuple(out["config"]["Ks"]), args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

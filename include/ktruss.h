@@ -56,14 +56,24 @@ extern "C" {
 #define KTRUSS_SCHED_FORCE_WAVE 3  /* every edge task on the wavefront-per-edge kernel (testing) */
 #define KTRUSS_SCHED_FORCE_HUB  4  /* every row on the workgroup-per-row kernel (testing) */
 
-/* Tuning knobs of the heuristic / learned schedules (0 = library default). */
+/* Tuning knobs (0 = library default). */
 typedef struct ktruss_tuning {
-    int32_t wave_min_work;   /* edge tasks with estimated merge length >= this use wavefront-per-edge */
-    int32_t hub_min_work;    /* rows with total estimated work >= this use workgroup-per-row */
-    int32_t hub_chunk_work;  /* target work per workgroup when a hub row is split */
-    int32_t rounds_per_sync; /* prune rounds replayed (hipGraph) per host convergence check */
-    int32_t reserved[4];
+    int32_t wave_min_work;   /* heuristic/learned: non-hub edge tasks whose merge length (row tail + row kappa)
+                                is at least this use wavefront-per-edge, the others thread-per-edge */
+    int32_t hub_min_work;    /* heuristic: rows kappa selected by at least this many tasks are hub rows */
+    int32_t hub_chunk_work;  /* learned: predicted shader cycles per hub item when a hub row is split */
+    int32_t rounds_per_sync; /* <= 1: host checks the fixpoint after every round (exact grids);
+                                >= 2: rounds are captured in a hipGraph and replayed this many at a time */
+    float learned_hub_min;   /* learned: rows whose predicted log2 cycles reach this are hub rows */
+    int32_t reserved[3];
 } ktruss_tuning;
+
+/* Cost model: 5 inputs -> 64 ReLU -> 64 ReLU -> 1 output, FP32.  Parameter
+ * vector layout: W1[64x5] (row j: weights into hidden unit j), b1[64],
+ * W2[64x64] (row k: weights into second-layer unit k), b2[64], w3[64], b3. */
+#define KTRUSS_MLP_IN 5
+#define KTRUSS_MLP_HIDDEN 64
+#define KTRUSS_MLP_PARAMS 4609
 
 /* A graph resident on the device plus its workspace.  Caller-owned POD. */
 typedef struct ktruss_graph {
@@ -225,6 +235,47 @@ int32_t ktruss_profile_enable(int32_t on);
  * bytes.  Any out pointer may be NULL.  E_INVALID for a kind outside 0..3.
  */
 int32_t ktruss_profile_read(int32_t kind, int64_t* launches, double* total_ms, int64_t* tasks, int64_t* bytes);
+
+/* ------------------------------------------------------------- cost model */
+/*
+ * The LEARNED schedule predicts, for every row kappa of A22 that the tasks of
+ * a pass select (Algorithm 3), the shader cycles its support work costs on
+ * the workgroup-per-hub-row kernel, from five features: its out-degree, log2
+ * of it, log2 of the sum of the out-degrees of the rows whose tasks select it,
+ * the pass index, and the fraction of the input's edges still alive.  Rows
+ * predicted expensive become hub rows, split into items of about
+ * tuning.hub_chunk_work predicted cycles; the other tasks go to the
+ * wavefront- or thread-per-edge kernels.  Scheduling only: results never
+ * depend on the model.  The model is trained on samples from
+ * ktruss_collect_row_costs with the calls below.
+ */
+
+/*
+ * ktruss_collect_row_costs — runs the fixpoint of g for K under the hub
+ * schedule with the hub kernel timed per row, and appends one sample per
+ * active row and pass: features (device float[capacity*5]) and the measured
+ * cost as log2(1 + shader cycles) (device float[capacity]).  count (host)
+ * receives the number of samples written (at most capacity).  Outputs of the
+ * truss itself are not produced.  Synchronises `stream`.
+ */
+int32_t ktruss_collect_row_costs(const ktruss_graph* g, int32_t K, float* features, float* costs, int32_t capacity,
+                                 int32_t* count, void* stream);
+
+/* Scratch bytes needed by ktruss_mlp_loss_grad for `rows` samples. */
+int64_t ktruss_mlp_workspace_bytes(int32_t rows);
+/* y[r] = network(x[r*5 .. r*5+4]) for r < rows.  params, x, y: device. */
+int32_t ktruss_mlp_forward(const float* params, const float* x, int32_t rows, float* y, void* stream);
+/*
+ * Mean squared error L = mean_r (y[r] - target[r])^2 and its gradient with
+ * respect to all KTRUSS_MLP_PARAMS parameters (device float out; loss may be
+ * NULL).  work: device scratch of ktruss_mlp_workspace_bytes(rows) bytes.
+ * The reduction order is fixed (results are deterministic).
+ */
+int32_t ktruss_mlp_loss_grad(const float* params, const float* x, const float* target, int32_t rows, float* loss,
+                             float* grad, void* work, int64_t work_bytes, void* stream);
+/* One Adam step (Kingma and Ba): m, v device float[KTRUSS_MLP_PARAMS] state; step counts from 1. */
+int32_t ktruss_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1,
+                        float beta2, float eps, void* stream);
 
 #ifdef __cplusplus
 }

@@ -75,6 +75,14 @@ FullLayout full_layout(int32_t n, int64_t m, int32_t G) {
     L.itemoff = take(vn);
     L.item_kappa = take(sizeof(int32_t) * (size_t)item_capacity(n, m));
     L.item_c0 = take(sizeof(int32_t) * (size_t)item_capacity(n, m));
+    L.item_c1 = take(sizeof(int32_t) * (size_t)item_capacity(n, m));
+    L.insum = take(sizeof(unsigned long long) * ((size_t)n + 1));
+    L.cycles = take(sizeof(unsigned long long) * ((size_t)n + 1));
+    L.act_off = take(vn);
+    L.act_list = take(vn);
+    L.feats = take(sizeof(float) * KTRUSS_MLP_IN * ((size_t)n + 1));
+    L.pred = take(sizeof(float) * ((size_t)n + 1));
+    L.chunk_sz = take(vn);
     L.is_hub = take((size_t)n + 1);
     L.wave_tasks = take(em);
     L.thread_tasks = take(em);
@@ -121,6 +129,14 @@ Work carve(void* work, int32_t n, int64_t m, int32_t G) {
     w.sc.itemoff = (int32_t*)(base + L.itemoff);
     w.sc.item_kappa = (int32_t*)(base + L.item_kappa);
     w.sc.item_c0 = (int32_t*)(base + L.item_c0);
+    w.sc.item_c1 = (int32_t*)(base + L.item_c1);
+    w.sc.insum = (unsigned long long*)(base + L.insum);
+    w.sc.cycles = (unsigned long long*)(base + L.cycles);
+    w.sc.act_off = (int32_t*)(base + L.act_off);
+    w.sc.act_list = (int32_t*)(base + L.act_list);
+    w.sc.feats = (float*)(base + L.feats);
+    w.sc.pred = (float*)(base + L.pred);
+    w.sc.chunk_sz = (int32_t*)(base + L.chunk_sz);
     w.sc.is_hub = (uint8_t*)(base + L.is_hub);
     w.sc.wave_tasks = (int32_t*)(base + L.wave_tasks);
     w.sc.thread_tasks = (int32_t*)(base + L.thread_tasks);
@@ -277,8 +293,10 @@ struct PassDims {
     int32_t n_thread; // thread tasks
 };
 
-// One support pass over buffer p.
-int32_t support_pass(int sched, int32_t n, const Work& w, int p, const PassDims& dm, hipStream_t s) {
+// One support pass over buffer p.  cycles: per-row hub timing (cost-model
+// samples), or null.
+int32_t support_pass(int sched, int32_t n, const Work& w, int p, const PassDims& dm, hipStream_t s,
+                     unsigned long long* cycles = nullptr) {
     const Buf& x = w.b[p];
     Timer tp;
     int32_t rc = timer_begin(tp, 0, dm.m, 16 * (int64_t)dm.m + 4 * ((int64_t)n + 1), s);
@@ -293,7 +311,7 @@ int32_t support_pass(int sched, int32_t n, const Work& w, int p, const PassDims&
         });
     } else {
         rc = timed_launch(3, dm.items, s, [&] {
-            return launch_support_hub(x, w.c[p], w.sc.item_kappa, w.sc.item_c0, dm.items, w.ctl, s);
+            return launch_support_hub(x, w.c[p], w.sc, dm.items, w.ctl, cycles, s);
         });
         if (rc == KTRUSS_OK && sched != KTRUSS_SCHED_FORCE_HUB) {
             rc = timed_launch(2, dm.n_wave, s, [&] {
@@ -326,12 +344,47 @@ struct RunSpec {
     int32_t G;               // graphs (batched form), 0 otherwise
     const int32_t* K;        // device int32[G] (batched form)
     int32_t* rounds_dev;     // device int32[G] (batched form)
+    const float* mlp;        // cost-model parameters (LEARNED schedule)
+    // cost sampling (ktruss_collect_row_costs)
+    bool collect;
+    int32_t capacity;
+    float* out_x;
+    float* out_y;
 };
+
+RunSpec make_spec(int32_t n, int32_t m, const int32_t* rowptr, const int32_t* col, int sched, const ktruss_tuning& t,
+                  const float* mlp) {
+    RunSpec r{};
+    r.n = n;
+    r.m = m;
+    r.rowptr = rowptr;
+    r.col = col;
+    r.sched = sched;
+    r.tuning = t;
+    r.mlp = mlp;
+    return r;
+}
+
+bool needs_features(const RunSpec& r) { return r.collect || (r.sched == KTRUSS_SCHED_LEARNED && r.mlp); }
 
 int32_t prepare(const RunSpec& r, Work& w, int p, int32_t m_hint, hipStream_t s) {
     if (!uses_csc(r.sched)) return KTRUSS_OK;
-    HIP_TRY(launch_prepare_pass(w.b[p], w.c[p], r.n, r.sched, r.tuning, nullptr, w.sc, w.ctl, p, m_hint, s),
+    HIP_TRY(launch_prepare_pass(w.b[p], w.c[p], r.n, r.sched, r.tuning, r.sched == KTRUSS_SCHED_LEARNED ? r.mlp : nullptr,
+                                r.m, r.collect, w.sc, w.ctl, p, m_hint, s),
             "prepare pass");
+    return KTRUSS_OK;
+}
+
+// Work before the first round: buffer 0 := the input, in-edge lists, the
+// per-run row statistics of the cost model, the first preparation.
+int32_t set_up_run(const RunSpec& r, Work& w, hipStream_t s) {
+    HIP_TRY(launch_init_run(w.b[0], r.rowptr, r.col, r.n, r.m, s), "init");
+    if (uses_csc(r.sched)) HIP_TRY(launch_build_csc(w.b[0], w.c[0], r.n, r.m, w.sc, s), "in-edge lists");
+    if (needs_features(r)) {
+        HIP_TRY(launch_in_outdeg_sum(w.b[0], w.c[0], r.n, r.m, w.sc, s), "row statistics");
+        hipError_t e = hipMemsetAsync(w.sc.cycles, 0, sizeof(unsigned long long) * ((size_t)r.n + 1), s);
+        if (e != hipSuccess) return fail_hip(e, "zero cycles");
+    }
     return KTRUSS_OK;
 }
 
@@ -340,8 +393,10 @@ int32_t prepare(const RunSpec& r, Work& w, int p, int32_t m_hint, hipStream_t s)
 // pass.  No host interaction: every kernel reads its counts from the control
 // block and does nothing once the fixpoint is reached.
 int32_t enqueue_round(const RunSpec& r, Work& w, int p, const PassDims& dm, hipStream_t s) {
-    int32_t rc = support_pass(r.sched, r.n, w, p, dm, s);
+    int32_t rc = support_pass(r.sched, r.n, w, p, dm, s, r.collect ? w.sc.cycles : nullptr);
     if (rc != KTRUSS_OK) return rc;
+    if (r.collect)
+        HIP_TRY(launch_append_costs(w.sc, r.n, r.capacity, r.out_x, r.out_y, w.ctl, s), "cost samples");
     if (r.G > 0) HIP_TRY(launch_batch_status(w.b[p], w.batch, r.G, r.K, r.rounds_dev, w.ctl, s), "batch status");
     const bool csc = uses_csc(r.sched);
     HIP_TRY(launch_compact(w.b[p], w.b[1 - p], csc ? &w.c[p] : nullptr, csc ? &w.c[1 - p] : nullptr, r.n, 0, r.thr,
@@ -534,9 +589,10 @@ int32_t ktruss_support(const ktruss_graph* g, const uint8_t* alive, int32_t* sup
     rc = validate_on_device(g->rowptr, g->col, n, m, w, w.b[0].src, s);
     if (rc != KTRUSS_OK) return rc;
     if (m == 0) return KTRUSS_OK;
-    const bool csc = uses_csc(g->schedule);
-    HIP_TRY(launch_init_run(w.b[0], g->rowptr, g->col, n, m, s), "init");
-    if (csc) HIP_TRY(launch_build_csc(w.b[0], w.c[0], n, m, w.sc, s), "in-edge lists");
+    const RunSpec r = make_spec(n, m, g->rowptr, g->col, g->schedule, g->tuning, g->mlp_params);
+    const bool csc = uses_csc(r.sched);
+    rc = set_up_run(r, w, s);
+    if (rc != KTRUSS_OK) return rc;
     HIP_TRY(hipMemsetAsync(support, 0, sizeof(int32_t) * (size_t)m, s), "zero support");
     int p = 0;
     if (alive) {
@@ -546,13 +602,12 @@ int32_t ktruss_support(const ktruss_graph* g, const uint8_t* alive, int32_t* sup
         p = 1;
         HIP_TRY(launch_set_final(w.ctl, 1, s), "final buffer");
     }
-    RunSpec r{n, m, g->rowptr, g->col, g->schedule, g->tuning, 0, 0, nullptr, nullptr};
     rc = prepare(r, w, p, m, s);
     Ctl h{};
     if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
     if (rc != KTRUSS_OK) return rc;
     const PassDims dm{h.m_buf[p], h.n_items, h.n_wave, h.n_thread};
-    rc = support_pass(g->schedule, n, w, p, dm, s);
+    rc = support_pass(r.sched, n, w, p, dm, s);
     if (rc != KTRUSS_OK) return rc;
     HIP_TRY(launch_scatter_out(w.b[0], w.b[1], w.ctl, nullptr, support, m, s), "scatter");
     HIP_TRY(hipStreamSynchronize(s), "support sync");
@@ -587,12 +642,12 @@ int32_t ktruss_run(const ktruss_graph* g, int32_t K, uint8_t* mask, int32_t* sup
         if (rounds) *rounds = 1;
         return KTRUSS_OK;
     }
-    const bool csc = uses_csc(g->schedule);
-    HIP_TRY(launch_init_run(w.b[0], g->rowptr, g->col, n, m, s), "init");
-    if (csc) HIP_TRY(launch_build_csc(w.b[0], w.c[0], n, m, w.sc, s), "in-edge lists");
+    RunSpec r = make_spec(n, m, g->rowptr, g->col, g->schedule, g->tuning, g->mlp_params);
+    r.thr = K - 2;
+    rc = set_up_run(r, w, s);
+    if (rc != KTRUSS_OK) return rc;
     HIP_TRY(hipMemsetAsync(mask, 0, (size_t)m, s), "zero mask");
     HIP_TRY(hipMemsetAsync(support, 0, sizeof(int32_t) * (size_t)m, s), "zero support");
-    RunSpec r{n, m, g->rowptr, g->col, g->schedule, g->tuning, K - 2, 0, nullptr, nullptr};
     rc = prepare(r, w, 0, m, s);
     if (rc != KTRUSS_OK) return rc;
     Ctl h{};
@@ -632,26 +687,106 @@ int32_t ktruss_run_batched(const ktruss_batch* b, const int32_t* K, uint8_t* mas
     int32_t err = 0;
     HIP_TRY(hipMemcpyAsync(&err, &w.ctl->err, sizeof(err), hipMemcpyDeviceToHost, s), "batch check readback");
     HIP_TRY(hipStreamSynchronize(s), "batch check sync");
-    if (err) return fail(KTRUSS_E_INVALID, "malformed batch (check bits 0x%x: 32 vertex offsets or K < 2, 64 edge between graphs)", err);
+    if (err)
+        return fail(KTRUSS_E_INVALID,
+                    "malformed batch (check bits 0x%x: 32 vertex offsets or K < 2, 64 edge between graphs)", err);
     HIP_TRY(launch_batch_reset(w.batch, G, rounds, s), "batch reset");
-    HIP_TRY(launch_init_run(w.b[0], b->rowptr, b->col, n, m, s), "init");
     if (m == 0) {
         // every graph is empty: one pass that removes nothing
+        HIP_TRY(launch_init_run(w.b[0], b->rowptr, b->col, n, m, s), "init");
         HIP_TRY(launch_batch_status(w.b[0], w.batch, G, K, rounds, w.ctl, s), "batch status");
         HIP_TRY(hipStreamSynchronize(s), "batch sync");
         return KTRUSS_OK;
     }
-    const bool csc = uses_csc(b->schedule);
-    if (csc) HIP_TRY(launch_build_csc(w.b[0], w.c[0], n, m, w.sc, s), "in-edge lists");
+    RunSpec r = make_spec(n, m, b->rowptr, b->col, b->schedule, b->tuning, nullptr);
+    r.G = G;
+    r.K = K;
+    r.rounds_dev = rounds;
+    rc = set_up_run(r, w, s);
+    if (rc != KTRUSS_OK) return rc;
     HIP_TRY(hipMemsetAsync(mask, 0, (size_t)m, s), "zero mask");
     HIP_TRY(hipMemsetAsync(support, 0, sizeof(int32_t) * (size_t)m, s), "zero support");
-    RunSpec r{n, m, b->rowptr, b->col, b->schedule, b->tuning, 0, G, K, rounds};
     rc = prepare(r, w, 0, m, s);
     if (rc != KTRUSS_OK) return rc;
     Ctl h{};
     rc = run_rounds(r, w, s, h);
     if (rc != KTRUSS_OK) return rc;
     HIP_TRY(hipStreamSynchronize(s), "batch sync");
+    return KTRUSS_OK;
+}
+
+// ---------------------------------------------------------------- cost model
+
+int32_t ktruss_collect_row_costs(const ktruss_graph* g, int32_t K, float* features, float* costs, int32_t capacity,
+                                 int32_t* count, void* stream) {
+    clear_error();
+    int32_t rc = check_graph(g, true);
+    if (rc != KTRUSS_OK) return rc;
+    if (K < 2) return fail(KTRUSS_E_INVALID, "K must be >= 2 (got %d)", K);
+    if (capacity < 0 || (capacity > 0 && (!features || !costs)) || !count)
+        return fail(KTRUSS_E_INVALID, "sample buffers are null or capacity < 0");
+    hipStream_t s = (hipStream_t)stream;
+    Work w = carve(g->work, g->n, g->m, 0);
+    const int32_t n = g->n, m = (int32_t)g->m;
+    rc = validate_on_device(g->rowptr, g->col, n, m, w, w.b[0].src, s);
+    if (rc != KTRUSS_OK) return rc;
+    *count = 0;
+    if (m == 0) return KTRUSS_OK;
+    ktruss_tuning t = g->tuning;
+    t.rounds_per_sync = 0;
+    RunSpec r = make_spec(n, m, g->rowptr, g->col, KTRUSS_SCHED_FORCE_HUB, t, nullptr);
+    r.thr = K - 2;
+    r.collect = true;
+    r.capacity = capacity;
+    r.out_x = features;
+    r.out_y = costs;
+    rc = set_up_run(r, w, s);
+    if (rc == KTRUSS_OK) rc = prepare(r, w, 0, m, s);
+    if (rc != KTRUSS_OK) return rc;
+    Ctl h{};
+    rc = run_rounds(r, w, s, h);
+    if (rc != KTRUSS_OK) return rc;
+    *count = h.n_samples;
+    return KTRUSS_OK;
+}
+
+int64_t ktruss_mlp_workspace_bytes(int32_t rows) {
+    clear_error();
+    if (rows < 0) return fail(KTRUSS_E_INVALID, "rows must be >= 0");
+    const int64_t nblk = mlp_grad_blocks(rows);
+    return (nblk * KTRUSS_MLP_PARAMS + nblk) * (int64_t)sizeof(float);
+}
+
+int32_t ktruss_mlp_forward(const float* params, const float* x, int32_t rows, float* y, void* stream) {
+    clear_error();
+    if (rows < 0) return fail(KTRUSS_E_INVALID, "rows must be >= 0");
+    if (rows > 0 && (!params || !x || !y)) return fail(KTRUSS_E_INVALID, "null pointer");
+    HIP_TRY(launch_mlp_forward(params, x, rows, y, (hipStream_t)stream), "mlp forward");
+    return KTRUSS_OK;
+}
+
+int32_t ktruss_mlp_loss_grad(const float* params, const float* x, const float* target, int32_t rows, float* loss,
+                             float* grad, void* work, int64_t work_bytes, void* stream) {
+    clear_error();
+    if (rows <= 0) return fail(KTRUSS_E_INVALID, "rows must be > 0");
+    if (!params || !x || !target || !grad) return fail(KTRUSS_E_INVALID, "null pointer");
+    const int64_t need = ktruss_mlp_workspace_bytes(rows);
+    const int32_t rc = check_work(work, work_bytes, need);
+    if (rc != KTRUSS_OK) return rc;
+    const int64_t nblk = mlp_grad_blocks(rows);
+    float* partial = (float*)work;
+    float* loss_part = partial + nblk * KTRUSS_MLP_PARAMS;
+    HIP_TRY(launch_mlp_loss_grad(params, x, target, rows, partial, loss_part, grad, loss, (hipStream_t)stream),
+            "mlp gradient");
+    return KTRUSS_OK;
+}
+
+int32_t ktruss_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float beta1,
+                        float beta2, float eps, void* stream) {
+    clear_error();
+    if (!params || !grad || !m || !v) return fail(KTRUSS_E_INVALID, "null pointer");
+    if (step < 1) return fail(KTRUSS_E_INVALID, "step counts from 1");
+    HIP_TRY(launch_mlp_adam(params, grad, m, v, step, lr, beta1, beta2, eps, (hipStream_t)stream), "adam");
     return KTRUSS_OK;
 }
 

@@ -21,6 +21,12 @@ constexpr int kSpanWords = kSpanCap / 32;
 constexpr int kKeyCap = 2 * kSpanWords;  // longest row kappa staged in LDS (keys / accumulators)
 constexpr int kHubMaxGrid = 256 * 8;     // persistent hub grid: 8 workgroups per CU
 constexpr int kStreamMaxGrid = 256 * 16; // grid-stride cap of the thread/wave task kernels
+constexpr int kMlpGradMaxBlocks = 512;   // workgroups of the cost-model gradient kernel
+
+// learned schedule defaults (predicted log2 shader cycles of a row's hub work)
+constexpr float kDefaultLearnedHubMin = 16.0f;
+constexpr float kDefaultLearnedChunk = 400000.0f;
+constexpr int kMinLearnedChunk = 16;     // fewest tasks per hub item
 
 // static degree heuristic defaults
 constexpr int kDefaultHubMinIn = 8;    // in-edges for a row kappa to be a hub row
@@ -39,6 +45,8 @@ struct Ctl {
     int32_t n_wave;      // wavefront-per-edge tasks of the current pass
     int32_t n_thread;    // thread-per-edge tasks of the current pass
     int32_t item_next;   // next hub item to take (persistent hub kernel)
+    int32_t n_active;    // rows with support work in the current pass (learned schedule, sampling)
+    int32_t n_samples;   // cost-model samples written so far
     int64_t removed_total;
 };
 
@@ -72,6 +80,14 @@ struct Scratch {
     int32_t* itemoff;     // int32[n+1]
     int32_t* item_kappa;  // int32[item capacity]
     int32_t* item_c0;     // int32[item capacity]
+    int32_t* item_c1;     // int32[item capacity]
+    unsigned long long* insum;   // uint64[n]: sum of in-neighbour out-degrees
+    unsigned long long* cycles;  // uint64[n]: measured hub cycles per row (sampling)
+    int32_t* act_off;     // int32[n+1]
+    int32_t* act_list;    // int32[n]
+    float* feats;         // float[n*5]
+    float* pred;          // float[n]
+    int32_t* chunk_sz;    // int32[n]
     uint8_t* is_hub;      // uint8[n]
     int32_t* wave_tasks;  // int32[m]
     int32_t* thread_tasks;// int32[m]
@@ -92,14 +108,15 @@ struct BatchCtx {
 struct Layout {
     size_t col[2], src[2], eid[2], S[2], rowptr[2];
     size_t cedge[2], cptr[2];
-    size_t xscan, cxscan, blockcnt, blockoff, blockcnt2, blockoff2, tmp_n, itemoff, item_kappa, item_c0, is_hub,
-        wave_tasks, thread_tasks;
+    size_t xscan, cxscan, blockcnt, blockoff, blockcnt2, blockoff2, tmp_n, itemoff, item_kappa, item_c0, item_c1,
+        is_hub, wave_tasks, thread_tasks, insum, cycles, act_off, act_list, feats, pred, chunk_sz;
     size_t ctl;        // Ctl
     size_t total;
 };
 
-// Upper bound on hub items: one per row plus one per kHubChunk edges.
-inline int64_t item_capacity(int32_t n, int64_t m) { return (int64_t)n + m / kHubChunk + 1; }
+// Upper bound on hub items: one per row plus one per kMinLearnedChunk edges
+// (the smallest split the learned schedule makes).
+inline int64_t item_capacity(int32_t n, int64_t m) { return (int64_t)n + m / kMinLearnedChunk + 1; }
 
 Layout layout(int32_t n, int64_t m);
 

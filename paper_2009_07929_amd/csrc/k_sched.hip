@@ -131,30 +131,162 @@ void device_scan(const F& f, int32_t N, const Ctl* ctl, Scratch& sc, int32_t* ou
 struct HubChunks {
     const int32_t* rowptr;
     const int32_t* cptr;
-    const uint8_t* is_hub;  // per row, or null = every row with work
+    const uint8_t* is_hub;    // per row, or null = every row with work
+    const int32_t* chunk_sz;  // tasks per item of each row (<= kHubChunk), or null = kHubChunk
+    __device__ int32_t size(int32_t k) const { return chunk_sz ? chunk_sz[k] : kHubChunk; }
     __device__ int32_t operator()(int32_t k) const {
         const int32_t indeg = cptr[k + 1] - cptr[k];
         const int32_t d = rowptr[k + 1] - rowptr[k];
         if (indeg == 0 || d == 0) return 0;
         if (is_hub && !is_hub[k]) return 0;
-        return (indeg + kHubChunk - 1) / kHubChunk;
+        const int32_t cs = size(k);
+        return (indeg + cs - 1) / cs;
     }
 };
 
 __global__ __launch_bounds__(kBlock) void k_hub_items(HubChunks f, int32_t n, const int32_t* __restrict__ itemoff,
                                                     int32_t* __restrict__ item_kappa, int32_t* __restrict__ item_c0,
-                                                    const Ctl* __restrict__ ctl) {
+                                                    int32_t* __restrict__ item_c1, const Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k == 0) const_cast<Ctl*>(ctl)->item_next = 0;
     if (k >= n) return;
     const int32_t nch = f((int32_t)k);
+    if (nch == 0) return;
     const int32_t o = itemoff[k];
-    const int32_t c0 = f.cptr[k];
+    const int32_t c0 = f.cptr[k], cend = f.cptr[k + 1];
+    const int32_t cs = f.size((int32_t)k);
     for (int32_t j = 0; j < nch; ++j) {
         item_kappa[o + j] = (int32_t)k;
-        item_c0[o + j] = c0 + j * kHubChunk;
+        item_c0[o + j] = c0 + j * cs;
+        item_c1[o + j] = min(c0 + (j + 1) * cs, cend);
     }
+}
+
+// ---- learned schedule: per-row features and cost-model bins
+
+// Rows kappa that carry support work in the current pass (in-edges and a
+// non-empty row).
+struct ActiveRow {
+    const int32_t* rowptr;
+    const int32_t* cptr;
+    __device__ int32_t operator()(int32_t k) const {
+        return (cptr[k + 1] > cptr[k] && rowptr[k + 1] > rowptr[k]) ? 1 : 0;
+    }
+};
+
+__global__ __launch_bounds__(kBlock) void k_active_list(ActiveRow f, int32_t n, const int32_t* __restrict__ off,
+                                                      int32_t* __restrict__ list, const Ctl* __restrict__ ctl) {
+    if (ctl && ctl->done) return;
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k < n && f((int32_t)k)) list[off[k]] = (int32_t)k;
+}
+
+// For every row kappa: sum over its in-edges (i, kappa) of the out-degree of
+// row i ("sum of neighbour out-degrees").  The in-edge lists are grouped by
+// kappa, so a wave-level segmented scan adds each run and its last lane
+// issues one atomic per run piece.
+__global__ __launch_bounds__(kBlock) void k_in_outdeg_sum(Buf x, Csc c, int32_t m, unsigned long long* __restrict__ sum) {
+    const int32_t i = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    const int lane = __lane_id();
+    int32_t key = -1;
+    long long v = 0;
+    if (i < m) {
+        const int32_t e = c.edge[i];
+        const int32_t r = x.src[e];
+        key = x.col[e];
+        v = x.rowptr[r + 1] - x.rowptr[r];
+    }
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long u = __shfl_up(v, o);
+        const int32_t kk = __shfl_up(key, o);
+        if (lane >= o && kk == key) v += u;
+    }
+    const int32_t next = __shfl_down(key, 1);
+    const bool tail = lane == 63 || next != key;
+    if (i < m && tail) atomicAdd(&sum[key], (unsigned long long)v);
+}
+
+// Features of active row kappa (the cost model's inputs): out-degree,
+// log2 out-degree, log2 of the sum of in-neighbour out-degrees, pass index,
+// fraction of the input's edges still alive.
+__device__ __forceinline__ void row_features(const int32_t* rowptr, const unsigned long long* insum, int32_t k,
+                                             int32_t pass, float alive, float* f) {
+    const float d = (float)(rowptr[k + 1] - rowptr[k]);
+    f[0] = d * (1.f / 1024.f);
+    f[1] = log2f(1.f + d) * (1.f / 12.f);
+    f[2] = log2f(1.f + (float)insum[k]) * (1.f / 24.f);
+    f[3] = (float)pass * (1.f / 32.f);
+    f[4] = alive;
+}
+
+__global__ __launch_bounds__(kBlock) void k_row_features(const int32_t* __restrict__ rowptr,
+                                                       const unsigned long long* __restrict__ insum,
+                                                       const int32_t* __restrict__ list, const Ctl* __restrict__ ctl,
+                                                       int p, int32_t m0, float* __restrict__ feats) {
+    if (ctl->done) return;
+    const int32_t a = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (a >= ctl->n_active) return;
+    float f[KTRUSS_MLP_IN];
+    row_features(rowptr, insum, list[a], ctl->rounds, (float)ctl->m_buf[p] / (float)(m0 > 0 ? m0 : 1), f);
+#pragma unroll
+    for (int i = 0; i < KTRUSS_MLP_IN; ++i) feats[(int64_t)a * KTRUSS_MLP_IN + i] = f[i];
+}
+
+// Bins from the predicted log2 cycles of each active row: hub row if at least
+// hub_min; a hub row is split into items of about `target` predicted cycles.
+__global__ __launch_bounds__(kBlock) void k_learned_bins(const int32_t* __restrict__ list, const float* __restrict__ pred,
+                                                       const int32_t* __restrict__ cptr, float hub_min, float target,
+                                                       uint8_t* __restrict__ is_hub, int32_t* __restrict__ chunk_sz,
+                                                       const Ctl* __restrict__ ctl) {
+    if (ctl->done) return;
+    const int32_t a = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (a >= ctl->n_active) return;
+    const int32_t k = list[a];
+    const float lp = pred[a];
+    const bool hub = lp >= hub_min;
+    is_hub[k] = hub ? 1 : 0;
+    if (hub) {
+        const int32_t indeg = cptr[k + 1] - cptr[k];
+        const float pieces = fminf(exp2f(fminf(lp, 40.f)) / target, (float)indeg);
+        int32_t cs = (int32_t)ceilf((float)indeg / fmaxf(pieces, 1.f));
+        cs = max(kMinLearnedChunk, min(cs, kHubChunk));
+        chunk_sz[k] = cs;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u8(uint8_t* __restrict__ a, int32_t n, uint8_t v) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_u64(unsigned long long* __restrict__ a, int32_t n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) a[i] = 0ull;
+}
+
+// Training rows from a timed pass: features of every active row and its
+// measured support cycles as log2(1 + cycles), appended while capacity lasts.
+__global__ __launch_bounds__(kBlock) void k_append_costs(const int32_t* __restrict__ list, const float* __restrict__ feats,
+                                                       const unsigned long long* __restrict__ cycles, int32_t capacity,
+                                                       float* __restrict__ out_x, float* __restrict__ out_y,
+                                                       Ctl* ctl) {
+    if (ctl->done) return;
+    const int32_t n_act = ctl->n_active;
+    const int32_t base = ctl->n_samples;
+    const int32_t a = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (a < n_act && base + a < capacity) {
+        const int32_t k = list[a];
+#pragma unroll
+        for (int i = 0; i < KTRUSS_MLP_IN; ++i)
+            out_x[(int64_t)(base + a) * KTRUSS_MLP_IN + i] = feats[(int64_t)a * KTRUSS_MLP_IN + i];
+        out_y[base + a] = log2f(1.f + (float)cycles[k]);
+    }
+}
+
+__global__ void k_advance_samples(Ctl* ctl, int32_t capacity) {
+    if (threadIdx.x == 0 && !ctl->done) ctl->n_samples = min(ctl->n_samples + ctl->n_active, capacity);
 }
 
 // ---- static degree heuristic: which rows kappa are hub rows
@@ -276,21 +408,52 @@ hipError_t launch_build_csc(const Buf& b, const Csc& c, int32_t n, int32_t m, Sc
     return hipGetLastError();
 }
 
-hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched, const ktruss_tuning& t,
-                               const uint8_t* learned_hub, Scratch& sc, Ctl* ctl, int p, int32_t m_hint,
+hipError_t launch_in_outdeg_sum(const Buf& x, const Csc& c, int32_t n, int32_t m, Scratch& sc, hipStream_t s) {
+    k_fill_u64<<<grid_for(n), kBlock, 0, s>>>(sc.insum, n);
+    if (m > 0) k_in_outdeg_sum<<<grid_for(m), kBlock, 0, s>>>(x, c, m, sc.insum);
+    return hipGetLastError();
+}
+
+hipError_t launch_append_costs(Scratch& sc, int32_t n, int32_t capacity, float* out_x, float* out_y, Ctl* ctl,
                                hipStream_t s) {
+    k_append_costs<<<grid_for(n), kBlock, 0, s>>>(sc.act_list, sc.feats, sc.cycles, capacity, out_x, out_y, ctl);
+    k_advance_samples<<<1, 64, 0, s>>>(ctl, capacity);
+    k_fill_u64<<<grid_for(n), kBlock, 0, s>>>(sc.cycles, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched, const ktruss_tuning& t,
+                               const float* mlp, int32_t m0, bool features, Scratch& sc, Ctl* ctl, int p,
+                               int32_t m_hint, hipStream_t s) {
     const uint8_t* is_hub = nullptr;
-    if (sched == KTRUSS_SCHED_HEURISTIC) {
+    const int32_t* chunk = nullptr;
+    const bool learned = sched == KTRUSS_SCHED_LEARNED && mlp;
+    if (sched == KTRUSS_SCHED_HEURISTIC || (sched == KTRUSS_SCHED_LEARNED && !mlp)) {
         const int32_t hub_min_in = t.hub_min_work > 0 ? t.hub_min_work : kDefaultHubMinIn;
         k_heuristic_bins<<<grid_for(n), kBlock, 0, s>>>(x.rowptr, c.ptr, n, hub_min_in, sc.is_hub, ctl);
         is_hub = sc.is_hub;
-    } else if (sched == KTRUSS_SCHED_LEARNED) {
-        is_hub = learned_hub;
+    }
+    if (learned || features) {
+        // rows with work, their features (and, learned, the cost model's bins)
+        device_scan(ActiveRow{x.rowptr, c.ptr}, n, ctl, sc, sc.act_off, &ctl->n_active, s);
+        k_active_list<<<grid_for(n), kBlock, 0, s>>>(ActiveRow{x.rowptr, c.ptr}, n, sc.act_off, sc.act_list, ctl);
+        k_row_features<<<grid_for(n), kBlock, 0, s>>>(x.rowptr, sc.insum, sc.act_list, ctl, p, m0, sc.feats);
+    }
+    if (learned) {
+        hipError_t e = launch_mlp_forward_dev(mlp, sc.feats, &ctl->n_active, n, sc.pred, s);
+        if (e != hipSuccess) return e;
+        const float hub_min = t.learned_hub_min > 0.f ? t.learned_hub_min : kDefaultLearnedHubMin;
+        const float target = t.hub_chunk_work > 0 ? (float)t.hub_chunk_work : kDefaultLearnedChunk;
+        k_fill_u8<<<grid_for(n), kBlock, 0, s>>>(sc.is_hub, n, 0);
+        k_learned_bins<<<grid_for(n), kBlock, 0, s>>>(sc.act_list, sc.pred, c.ptr, hub_min, target, sc.is_hub,
+                                                       sc.chunk_sz, ctl);
+        is_hub = sc.is_hub;
+        chunk = sc.chunk_sz;
     }
     // hub items (every row with work under FORCE_HUB)
-    HubChunks hc{x.rowptr, c.ptr, is_hub};
+    HubChunks hc{x.rowptr, c.ptr, is_hub, chunk};
     device_scan(hc, n, ctl, sc, sc.itemoff, &ctl->n_items, s);
-    k_hub_items<<<grid_for(n), kBlock, 0, s>>>(hc, n, sc.itemoff, sc.item_kappa, sc.item_c0, ctl);
+    k_hub_items<<<grid_for(n), kBlock, 0, s>>>(hc, n, sc.itemoff, sc.item_kappa, sc.item_c0, sc.item_c1, ctl);
     if (is_hub) {
         const int32_t wave_min = t.wave_min_work > 0 ? t.wave_min_work : kDefaultWaveMin;
         TaskClass tc{x, c, is_hub, wave_min};

@@ -19,6 +19,8 @@ __global__ void k_ctl_reset(Ctl* ctl, int32_t m) {
         ctl->n_wave = 0;
         ctl->n_thread = 0;
         ctl->item_next = 0;
+        ctl->n_active = 0;
+        ctl->n_samples = 0;
         ctl->removed_total = 0;
     }
 }

@@ -117,7 +117,9 @@ __device__ __forceinline__ void wave_task(const Buf& x, int32_t e) {
 enum { kModeBitmap = 0, kModeKeys = 1, kModeGlobal = 2 };
 
 __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const int32_t* __restrict__ item_kappa,
-                                                           const int32_t* __restrict__ item_c0, Ctl* ctl) {
+                                                           const int32_t* __restrict__ item_c0,
+                                                           const int32_t* __restrict__ item_c1, Ctl* ctl,
+                                                           unsigned long long* __restrict__ cycles) {
     __shared__ uint2 s_bm[kSpanWords];   // rank bitmap {bits, set bits before this word}; or keys
     __shared__ int32_t s_acc[kKeyCap];
     __shared__ int32_t s_e[kHubChunk];
@@ -138,7 +140,8 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
         const int32_t* __restrict__ col = x.col;
         const int32_t k = item_kappa[it];
         const int32_t c0 = item_c0[it];
-        const int32_t c1 = min(c0 + kHubChunk, c.ptr[k + 1]);
+        const int32_t c1 = item_c1[it];
+        const unsigned long long t_start = cycles ? (unsigned long long)clock64() : 0ull;
         const int32_t ntask = c1 - c0;
         const int32_t rs = x.rowptr[k], d = x.rowptr[k + 1] - rs;
         const int t = threadIdx.x;
@@ -218,6 +221,10 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
                 const int32_t a = s_acc[q];
                 if (a) atomicAdd(&x.S[rs + q], a);
             }
+        if (cycles) {  // per-row cost samples for the cost model (shader clock)
+            __syncthreads();
+            if (t == 0) atomicAdd(&cycles[k], (unsigned long long)clock64() - t_start);
+        }
     }
 }
 
@@ -237,10 +244,11 @@ hipError_t launch_support_wave(const Buf& x, const int32_t* tasks, const int32_t
     return hipGetLastError();
 }
 
-hipError_t launch_support_hub(const Buf& x, const Csc& c, const int32_t* item_kappa, const int32_t* item_c0,
-                              int32_t n_items_hint, Ctl* ctl, hipStream_t s) {
+hipError_t launch_support_hub(const Buf& x, const Csc& c, const Scratch& sc, int32_t n_items_hint, Ctl* ctl,
+                              unsigned long long* cycles, hipStream_t s) {
     if (n_items_hint <= 0) return hipSuccess;
-    k_support_hub<<<min(n_items_hint, kHubMaxGrid), kHubThreads, 0, s>>>(x, c, item_kappa, item_c0, ctl);
+    k_support_hub<<<min(n_items_hint, kHubMaxGrid), kHubThreads, 0, s>>>(x, c, sc.item_kappa, sc.item_c0, sc.item_c1,
+                                                                        ctl, cycles);
     return hipGetLastError();
 }
 

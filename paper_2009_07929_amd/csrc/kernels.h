@@ -41,16 +41,36 @@ hipError_t launch_build_csc(const Buf& b, const Csc& c, int32_t n, int32_t m, Sc
 // Work lists of one support pass over buffer p: hub items (all rows with
 // work under FORCE_HUB; the hub rows of the heuristic or of `learned_hub`
 // otherwise) and, except under FORCE_HUB, the wavefront / thread task lists.
+// mlp: cost-model parameters (LEARNED; null falls back to the heuristic);
+// features: also build the active-row list and features (cost sampling);
+// m0: the input's edge count (alive-fraction feature).
 hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched, const ktruss_tuning& t,
-                               const uint8_t* learned_hub, Scratch& sc, Ctl* ctl, int p, int32_t m_hint,
-                               hipStream_t s);
+                               const float* mlp, int32_t m0, bool features, Scratch& sc, Ctl* ctl, int p,
+                               int32_t m_hint, hipStream_t s);
 
 // ---- support kernels (k_support.hip); count_dev points at the task count
 hipError_t launch_support_thread(const Buf& x, const int32_t* tasks, const int32_t* count_dev, int32_t n_hint,
                                  const Ctl* ctl, hipStream_t s);
 hipError_t launch_support_wave(const Buf& x, const int32_t* tasks, const int32_t* count_dev, int32_t n_hint,
                                const Ctl* ctl, hipStream_t s);
-hipError_t launch_support_hub(const Buf& x, const Csc& c, const int32_t* item_kappa, const int32_t* item_c0,
-                              int32_t n_items_hint, Ctl* ctl, hipStream_t s);
+// cycles: per-row shader-clock totals of the hub items (cost-model samples), or null
+hipError_t launch_support_hub(const Buf& x, const Csc& c, const Scratch& sc, int32_t n_items_hint, Ctl* ctl,
+                              unsigned long long* cycles, hipStream_t s);
+
+// ---- cost model (k_mlp.hip, k_sched.hip)
+int32_t mlp_grad_blocks(int32_t rows);
+hipError_t launch_mlp_forward(const float* params, const float* X, int32_t rows, float* Y, hipStream_t s);
+// rows read from device memory (upper bound rows_hint sizes the grid)
+hipError_t launch_mlp_forward_dev(const float* params, const float* X, const int32_t* rows_dev, int32_t rows_hint,
+                                  float* Y, hipStream_t s);
+hipError_t launch_mlp_loss_grad(const float* params, const float* X, const float* T, int32_t rows, float* partial,
+                                float* loss_part, float* grad, float* loss, hipStream_t s);
+hipError_t launch_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t step, float lr, float b1,
+                           float b2, float eps, hipStream_t s);
+// Sum of in-neighbour out-degrees of every row (once per run), and the
+// training-sample append after a timed pass.
+hipError_t launch_in_outdeg_sum(const Buf& x, const Csc& c, int32_t n, int32_t m, Scratch& sc, hipStream_t s);
+hipError_t launch_append_costs(Scratch& sc, int32_t n, int32_t capacity, float* out_x, float* out_y, Ctl* ctl,
+                               hipStream_t s);
 
 }  // namespace kt

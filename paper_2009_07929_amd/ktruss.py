@@ -31,7 +31,10 @@ class KtrussError(RuntimeError):
 class ktruss_tuning(ctypes.Structure):
     _fields_ = [("wave_min_work", ctypes.c_int32), ("hub_min_work", ctypes.c_int32),
                 ("hub_chunk_work", ctypes.c_int32), ("rounds_per_sync", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("learned_hub_min", ctypes.c_float), ("reserved", ctypes.c_int32 * 3)]
+
+
+MLP_IN, MLP_HIDDEN, MLP_PARAMS = 5, 64, 4609
 
 
 class ktruss_graph(ctypes.Structure):
@@ -120,6 +123,14 @@ def ktruss_build_csr(src, dst, n: int, order: int = 1):
     _check(load().ktruss_build_csr(_ptr(src), _ptr(dst), len(src), n, order, _ptr(rowptr), _ptr(col),
                                    len(col), _ptr(n2o), ctypes.byref(m)))
     return rowptr, col[: m.value].copy(), n2o[:n].copy()
+
+
+def build_csrs(pairs, order: int = 1, threads: int = 16):
+    """ktruss_build_csr over many graphs [(n, src, dst), ...] on a thread pool
+    (the C builder runs outside the interpreter lock).  Returns [(rowptr, col)]."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(lambda g: ktruss_build_csr(g[1], g[2], g[0], order)[:2], pairs))
 
 
 def ktruss_workspace_bytes(n: int, m: int, flags: int = 0) -> int:
@@ -240,10 +251,13 @@ def union_csr(graphs):
     edge_off[1:] = np.cumsum(ms)
     if vert_off[-1] > 2**31 - 2 or edge_off[-1] > 2**31 - 2:
         raise ValueError("batch too large for int32 offsets")
-    rowptr = np.concatenate([np.asarray(rp[:-1], np.int64) + edge_off[g] for g, (rp, _) in enumerate(graphs)]
-                            + [np.array([edge_off[-1]], np.int64)]).astype(np.int32)
-    col = (np.concatenate([np.asarray(c, np.int64) + vert_off[g] for g, (_, c) in enumerate(graphs)])
-           if edge_off[-1] else np.zeros(0, np.int64)).astype(np.int32)
+    rowptr = np.empty(vert_off[-1] + 1, np.int32)
+    col = np.empty(edge_off[-1], np.int32)
+    for g, (rp, c) in enumerate(graphs):
+        v0, v1, e0, e1 = vert_off[g], vert_off[g + 1], edge_off[g], edge_off[g + 1]
+        np.add(rp[:-1], np.int32(e0), out=rowptr[v0:v1], casting="unsafe")
+        np.add(c, np.int32(v0), out=col[e0:e1], casting="unsafe")
+    rowptr[-1] = edge_off[-1]
     return vert_off.astype(np.int32), rowptr, col
 
 
@@ -297,3 +311,66 @@ def ktruss_run_batched(b: Batch, K, mask=None, support=None, rounds=None, stream
     _check(load().ktruss_run_batched(ctypes.byref(b.c), _ptr(K), _ptr(mask), _ptr(support), _ptr(rounds),
                                      _stream(stream)))
     return mask[: b.m_total], support[: b.m_total], rounds[: b.G]
+
+
+# -------------------------------------------------------------------- cost model
+
+def _cost_model_sigs(lib):
+    i32, i64, p, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_float
+    G = ctypes.POINTER(ktruss_graph)
+    for name, args, res in (
+            ("ktruss_collect_row_costs", [G, i32, p, p, i32, ctypes.POINTER(ctypes.c_int32), p], i32),
+            ("ktruss_mlp_workspace_bytes", [i32], i64),
+            ("ktruss_mlp_forward", [p, p, i32, p, p], i32),
+            ("ktruss_mlp_loss_grad", [p, p, p, i32, p, p, p, i64, p], i32),
+            ("ktruss_mlp_adam", [p, p, p, p, i32, f32, f32, f32, f32, p], i32)):
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+
+
+def ktruss_collect_row_costs(g: Graph, K: int, capacity: int, stream=None):
+    """Per-row cost samples of a timed hub-schedule run: (features float[count,5], log2 cycles float[count])."""
+    import torch
+    lib = load()
+    _cost_model_sigs(lib)
+    X = torch.empty(max(capacity, 1) * MLP_IN, dtype=torch.float32, device=g.device)
+    Y = torch.empty(max(capacity, 1), dtype=torch.float32, device=g.device)
+    count = ctypes.c_int32()
+    _check(lib.ktruss_collect_row_costs(ctypes.byref(g.c), K, _ptr(X), _ptr(Y), capacity, ctypes.byref(count),
+                                        _stream(stream)))
+    c = count.value
+    return X[: c * MLP_IN].view(c, MLP_IN), Y[:c]
+
+
+def ktruss_mlp_forward(params, X, stream=None):
+    import torch
+    lib = load()
+    _cost_model_sigs(lib)
+    rows = X.shape[0]
+    Y = torch.empty(max(rows, 1), dtype=torch.float32, device=X.device)
+    _check(lib.ktruss_mlp_forward(_ptr(params), _ptr(X), rows, _ptr(Y), _stream(stream)))
+    return Y[:rows]
+
+
+def ktruss_mlp_loss_grad(params, X, T, work=None, stream=None):
+    """(loss tensor[1], grad tensor[4609]) of mean squared error on device."""
+    import torch
+    lib = load()
+    _cost_model_sigs(lib)
+    rows = X.shape[0]
+    nbytes = int(lib.ktruss_mlp_workspace_bytes(rows))
+    if work is None or work.numel() < nbytes:
+        work = torch.empty(max(nbytes, 16), dtype=torch.uint8, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+    _check(lib.ktruss_mlp_loss_grad(_ptr(params), _ptr(X), _ptr(T), rows, _ptr(loss), _ptr(grad), _ptr(work),
+                                    work.numel(), _stream(stream)))
+    return loss, grad
+
+
+def ktruss_mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    lib = load()
+    _cost_model_sigs(lib)
+    _check(lib.ktruss_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), step, lr, beta1, beta2, eps,
+                               _stream(stream)))

@@ -214,6 +214,8 @@ WORKLOADS = {
     "rmat-s22-ef16": Workload("rmat-s22-ef16", "rmat",
                               dict(scale=22, edge_factor=16, abc=(0.6, 0.2, 0.15), seed=22), (3, 6, 10)),
     "ba-4M-m8": Workload("ba-4M-m8", "ba", dict(n=4 * 1024 * 1024, m=8, seed=23), (3, 6, 10)),
+    # many small graphs of uneven sizes in one batched run (K per graph in 3..8)
+    "chunglu-batch-4096": Workload("chunglu-batch-4096", "batch", dict(count=4096, seed=5, nmin=64, nmax=20000)),
 }
 
 
@@ -234,11 +236,20 @@ def workload_pairs(name: str):
     raise KeyError(name)
 
 
-def batch_graphs(count: int = 4096, seed: int = 5, nmin: int = 64, nmax: int = 20000):
-    """The many-small-graphs workload: a list of (n, src, dst, K) Chung-Lu graphs."""
-    out = []
-    for g in range(count):
+def batch_graphs(count: int = 4096, seed: int = 5, nmin: int = 64, nmax: int = 20000, threads: int = 16):
+    """The many-small-graphs workload: a list of (n, src, dst, K) Chung-Lu graphs.
+
+    Graph g has n log-uniform in [nmin, nmax], power-law exponent uniform in
+    [2.1, 3.0], mean degree uniform in [4, 64] and K uniform in {3..8}, all drawn
+    from (seed, g); its pairs use seed * 1000003 + g.  Generated on `threads`
+    threads (the C generator runs outside the interpreter lock); the result does
+    not depend on the thread count."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    def one(g):
         n, gamma, dbar, K = batch_params(seed, g, nmin, nmax)
         _, s, d = chung_lu(n, gamma, dbar, seed * 1_000_003 + g)
-        out.append((n, s, d, K))
-    return out
+        return n, s, d, K
+
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(one, range(count)))
