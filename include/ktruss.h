@@ -65,7 +65,8 @@ typedef struct ktruss_tuning {
     int32_t rounds_per_sync; /* <= 1: host checks the fixpoint after every round (exact grids);
                                 >= 2: rounds are captured in a hipGraph and replayed this many at a time */
     float learned_hub_min;   /* learned: rows whose predicted log2 cycles reach this are hub rows */
-    int32_t reserved[3];
+    int32_t hub_chunk_tasks; /* heuristic/force-hub: tasks per hub item (clamped to 16..256) */
+    int32_t reserved[2];
 } ktruss_tuning;
 
 /* Cost model: 5 inputs -> 64 ReLU -> 64 ReLU -> 1 output, FP32.  Parameter

@@ -83,6 +83,7 @@ FullLayout full_layout(int32_t n, int64_t m, int32_t G) {
     L.feats = take(sizeof(float) * KTRUSS_MLP_IN * ((size_t)n + 1));
     L.pred = take(sizeof(float) * ((size_t)n + 1));
     L.chunk_sz = take(vn);
+    L.rs_hist = take(sizeof(int32_t) * (256 * (((size_t)m + kRsTile - 1) / kRsTile) + 1));
     L.is_hub = take((size_t)n + 1);
     L.wave_tasks = take(em);
     L.thread_tasks = take(em);
@@ -137,6 +138,7 @@ Work carve(void* work, int32_t n, int64_t m, int32_t G) {
     w.sc.feats = (float*)(base + L.feats);
     w.sc.pred = (float*)(base + L.pred);
     w.sc.chunk_sz = (int32_t*)(base + L.chunk_sz);
+    w.sc.rs_hist = (int32_t*)(base + L.rs_hist);
     w.sc.is_hub = (uint8_t*)(base + L.is_hub);
     w.sc.wave_tasks = (int32_t*)(base + L.wave_tasks);
     w.sc.thread_tasks = (int32_t*)(base + L.thread_tasks);

@@ -22,6 +22,7 @@ constexpr int kKeyCap = 2 * kSpanWords;  // longest row kappa staged in LDS (key
 constexpr int kHubMaxGrid = 256 * 8;     // persistent hub grid: 8 workgroups per CU
 constexpr int kStreamMaxGrid = 256 * 16; // grid-stride cap of the thread/wave task kernels
 constexpr int kMlpGradMaxBlocks = 512;   // workgroups of the cost-model gradient kernel
+constexpr int kRsTile = 4096;            // (column, edge) pairs per workgroup of the radix-sort transpose
 
 // learned schedule defaults (predicted log2 shader cycles of a row's hub work)
 constexpr float kDefaultLearnedHubMin = 16.0f;
@@ -88,6 +89,7 @@ struct Scratch {
     float* feats;         // float[n*5]
     float* pred;          // float[n]
     int32_t* chunk_sz;    // int32[n]
+    int32_t* rs_hist;     // int32[256 * ceil(m / kRsTile) + 1]: radix-sort digit histograms
     uint8_t* is_hub;      // uint8[n]
     int32_t* wave_tasks;  // int32[m]
     int32_t* thread_tasks;// int32[m]
@@ -109,7 +111,7 @@ struct Layout {
     size_t col[2], src[2], eid[2], S[2], rowptr[2];
     size_t cedge[2], cptr[2];
     size_t xscan, cxscan, blockcnt, blockoff, blockcnt2, blockoff2, tmp_n, itemoff, item_kappa, item_c0, item_c1,
-        is_hub, wave_tasks, thread_tasks, insum, cycles, act_off, act_list, feats, pred, chunk_sz;
+        is_hub, wave_tasks, thread_tasks, insum, cycles, act_off, act_list, feats, pred, chunk_sz, rs_hist;
     size_t ctl;        // Ctl
     size_t total;
 };

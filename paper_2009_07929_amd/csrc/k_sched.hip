@@ -21,20 +21,6 @@ __global__ __launch_bounds__(kBlock) void k_fill_i32(int32_t* __restrict__ a, in
     if (i < n) a[i] = v;
 }
 
-__global__ __launch_bounds__(kBlock) void k_indeg(const int32_t* __restrict__ col, int32_t m, int32_t* __restrict__ cnt) {
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e < m) atomicAdd(&cnt[col[e]], 1);
-}
-
-__global__ __launch_bounds__(kBlock) void k_csc_scatter(const int32_t* __restrict__ col, int32_t m,
-                                                      const int32_t* __restrict__ cptr, int32_t* __restrict__ cursor,
-                                                      int32_t* __restrict__ cedge) {
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= m) return;
-    const int32_t k = col[e];
-    cedge[cptr[k] + atomicAdd(&cursor[k], 1)] = (int32_t)e;
-}
-
 // ---- device-wide exclusive scan of f(0..N-1) into out[0..N], out[N] = total
 
 struct FromArray {
@@ -125,6 +111,86 @@ void device_scan(const F& f, int32_t N, const Ctl* ctl, Scratch& sc, int32_t* ou
     k_scan_write<F><<<G, kBlock, 0, s>>>(f, N, ctl, sc.blockoff, out, total_dst);
 }
 
+// ---- in-edge lists by a stable LSD radix sort of (column, edge) pairs
+//
+// 8-bit digits.  Per pass: every workgroup histograms the digits of its tile
+// of kRsTile pairs (LDS counters); the digit-major table of those histograms is
+// scanned; then every workgroup scatters its tile in order, ranking equal
+// digits within each wave by eight ballots (one per digit bit) and across
+// waves and sub-rounds through LDS counts.  Stable, so every column's list
+// stays in ascending edge order; no global atomics.
+
+constexpr int kRsItems = kRsTile / kBlock;
+
+__global__ __launch_bounds__(kBlock) void k_rs_hist(const int32_t* __restrict__ keys, int32_t N, int shift,
+                                                  int32_t nblk, int32_t* __restrict__ hist) {
+    __shared__ int s_h[256];
+    s_h[threadIdx.x] = 0;
+    __syncthreads();
+    const int32_t base = (int32_t)blockIdx.x * kRsTile;
+#pragma unroll
+    for (int j = 0; j < kRsItems; ++j) {
+        const int32_t e = base + j * kBlock + (int32_t)threadIdx.x;
+        if (e < N) atomicAdd(&s_h[(keys[e] >> shift) & 255], 1);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nblk + blockIdx.x] = s_h[threadIdx.x];
+}
+
+// vals == nullptr: the values are the positions themselves (first pass).
+__global__ __launch_bounds__(kBlock) void k_rs_scatter(const int32_t* __restrict__ keys, const int32_t* __restrict__ vals,
+                                                     int32_t N, int shift, int32_t nblk, const int32_t* __restrict__ off,
+                                                     int32_t* __restrict__ keys_out, int32_t* __restrict__ vals_out) {
+    __shared__ int s_run[256];
+    __shared__ int s_wcnt[kBlock / 64][256];
+    const int t = threadIdx.x, w = t >> 6;
+    s_run[t] = 0;
+#pragma unroll
+    for (int i = 0; i < kBlock / 64; ++i) s_wcnt[i][t] = 0;
+    __syncthreads();
+    const int32_t base = (int32_t)blockIdx.x * kRsTile;
+    const uint64_t lt = (1ull << __lane_id()) - 1ull;
+    for (int j = 0; j < kRsItems; ++j) {
+        const int32_t e = base + j * kBlock + t;
+        const bool valid = e < N;
+        const int32_t key = valid ? keys[e] : 0;
+        const int d = (key >> shift) & 255;
+        uint64_t match = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bb = __ballot(valid && ((d >> b) & 1));
+            match &= ((d >> b) & 1) ? bb : ~bb;
+        }
+        const int rank = __popcll(match & lt);
+        if (valid && rank == 0) s_wcnt[w][d] = __popcll(match);
+        __syncthreads();
+        if (valid) {
+            int pre = s_run[d];
+            for (int i = 0; i < w; ++i) pre += s_wcnt[i][d];
+            const int32_t pos = off[(int64_t)d * nblk + blockIdx.x] + pre + rank;
+            keys_out[pos] = key;
+            vals_out[pos] = vals ? vals[e] : e;
+        }
+        __syncthreads();
+        int add = 0;
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) {
+            add += s_wcnt[i][t];
+            s_wcnt[i][t] = 0;
+        }
+        s_run[t] += add;
+        __syncthreads();
+    }
+}
+
+// cptr[k] = first position of the sorted keys holding a value >= k, k in [0, n]
+__global__ __launch_bounds__(kBlock) void k_col_ptr(const int32_t* __restrict__ sorted, int32_t m, int32_t n,
+                                                  int32_t* __restrict__ cptr) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k > n) return;
+    cptr[k] = lower_bound_i32(sorted, m, (int32_t)k);
+}
+
 // ---- hub items
 
 // Number of hub items of row kappa: its in-edges cut into chunks of kHubChunk.
@@ -132,8 +198,9 @@ struct HubChunks {
     const int32_t* rowptr;
     const int32_t* cptr;
     const uint8_t* is_hub;    // per row, or null = every row with work
-    const int32_t* chunk_sz;  // tasks per item of each row (<= kHubChunk), or null = kHubChunk
-    __device__ int32_t size(int32_t k) const { return chunk_sz ? chunk_sz[k] : kHubChunk; }
+    const int32_t* chunk_sz;  // tasks per item of each row (<= kHubChunk), or null = chunk_all
+    int32_t chunk_all;
+    __device__ int32_t size(int32_t k) const { return chunk_sz ? chunk_sz[k] : chunk_all; }
     __device__ int32_t operator()(int32_t k) const {
         const int32_t indeg = cptr[k + 1] - cptr[k];
         const int32_t d = rowptr[k + 1] - rowptr[k];
@@ -399,12 +466,33 @@ __global__ __launch_bounds__(kBlock) void k_task_scatter(TaskClass tc, const Ctl
 
 }  // namespace
 
+// In-edge lists of buffer b by the stable radix sort above: edges sorted by
+// column, positions in ascending order within a column.
 hipError_t launch_build_csc(const Buf& b, const Csc& c, int32_t n, int32_t m, Scratch& sc, hipStream_t s) {
-    k_fill_i32<<<grid_for(n), kBlock, 0, s>>>(sc.tmp_n, n, 0);
-    if (m > 0) k_indeg<<<grid_for(m), kBlock, 0, s>>>(b.col, m, sc.tmp_n);
-    device_scan(FromArray{sc.tmp_n}, n, nullptr, sc, c.ptr, nullptr, s);
-    k_fill_i32<<<grid_for(n), kBlock, 0, s>>>(sc.tmp_n, n, 0);
-    if (m > 0) k_csc_scatter<<<grid_for(m), kBlock, 0, s>>>(b.col, m, c.ptr, sc.tmp_n, c.edge);
+    if (m == 0) {
+        k_fill_i32<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(c.ptr, n + 1, 0);
+        return hipGetLastError();
+    }
+    int bits = 0;
+    while (bits < 31 && ((int64_t)(n - 1) >> bits) != 0) ++bits;
+    const int passes = bits <= 8 ? 1 : (bits + 7) / 8;
+    const int32_t nblk = (int32_t)(((int64_t)m + kRsTile - 1) / kRsTile);
+    const int32_t nh = 256 * nblk;
+    int32_t* kbuf[2] = {sc.xscan, sc.wave_tasks};
+    int32_t* vbuf[2] = {sc.cxscan, sc.thread_tasks};
+    const int32_t* kin = b.col;
+    const int32_t* vin = nullptr;
+    for (int p = 0; p < passes; ++p) {
+        const int shift = 8 * p;
+        int32_t* kout = kbuf[p & 1];
+        int32_t* vout = p == passes - 1 ? c.edge : vbuf[p & 1];
+        k_rs_hist<<<nblk, kBlock, 0, s>>>(kin, m, shift, nblk, sc.rs_hist);
+        device_scan(FromArray{sc.rs_hist}, nh, nullptr, sc, sc.rs_hist, nullptr, s);
+        k_rs_scatter<<<nblk, kBlock, 0, s>>>(kin, vin, m, shift, nblk, sc.rs_hist, kout, vout);
+        kin = kout;
+        vin = vout;
+    }
+    k_col_ptr<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(kin, m, n, c.ptr);
     return hipGetLastError();
 }
 
@@ -451,7 +539,9 @@ hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched,
         chunk = sc.chunk_sz;
     }
     // hub items (every row with work under FORCE_HUB)
-    HubChunks hc{x.rowptr, c.ptr, is_hub, chunk};
+    int32_t chunk_all = t.hub_chunk_tasks > 0 ? t.hub_chunk_tasks : kHubChunk;
+    chunk_all = max(kMinLearnedChunk, min(chunk_all, kHubChunk));  // item capacity assumes >= kMinLearnedChunk
+    HubChunks hc{x.rowptr, c.ptr, is_hub, chunk, chunk_all};
     device_scan(hc, n, ctl, sc, sc.itemoff, &ctl->n_items, s);
     k_hub_items<<<grid_for(n), kBlock, 0, s>>>(hc, n, sc.itemoff, sc.item_kappa, sc.item_c0, sc.item_c1, ctl);
     if (is_hub) {

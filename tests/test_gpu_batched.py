@@ -134,3 +134,28 @@ def test_batched_rejects_malformed():
     with pytest.raises(kt().KtrussError) as ei:
         kt().ktruss_run_batched(b, K2)
     assert ei.value.code == kt().E_INVALID
+
+
+def test_autotuner_picks_a_bit_exact_config(tmp_path, rmat12):
+    import torch
+    from paper_2009_07929_amd import autotune
+    n, s, d = rmat12
+    rp, col, _ = kt().ktruss_build_csr(s, d, n)
+    g = kt().Graph(rp, col, device="cuda")
+    path = str(tmp_path / "cache.json")
+    key, best, t = autotune.tune_graph(g, 5, reps=1, path=path, rowptr=rp)
+    assert autotune.tuned_config(key, path) == best and t > 0
+    mask, sup, rounds = kt().ktruss_run(g, 5)
+    torch.cuda.synchronize()
+    om, osup, orounds = oracle.truss(rp, col, 5, "P")
+    assert np.array_equal(mask.cpu().numpy(), om) and np.array_equal(sup.cpu().numpy(), osup) and rounds == orounds
+    graphs, K = mixed_graphs(20, 9)
+    b = kt().Batch(graphs, device="cuda")
+    key, best, t = autotune.tune_batch(b, torch.from_numpy(K).cuda(), reps=1, path=path)
+    mask, sup, rounds = kt().ktruss_run_batched(b, K)
+    torch.cuda.synchronize()
+    eo = b.edge_offsets()
+    for gi, (rp2, col2) in enumerate(graphs):
+        om, osup, orounds = oracle.truss(rp2, col2, int(K[gi]), "P")
+        assert np.array_equal(mask.cpu().numpy()[eo[gi]:eo[gi + 1]], om)
+        assert int(rounds[gi].item()) == orounds
