@@ -133,7 +133,8 @@ def single_sweep(args, kt, torch):
     torch.cuda.synchronize()
     launches, sup_ms, edge_tasks, nbytes = kt.ktruss_profile_read(kt.PROFILE_PASS)
     kinds = {}
-    for name, kind in (("thread", kt.PROFILE_THREAD), ("wave", kt.PROFILE_WAVE), ("hub", kt.PROFILE_HUB)):
+    for name, kind in (("thread", kt.PROFILE_THREAD), ("wave", kt.PROFILE_WAVE), ("hub", kt.PROFILE_HUB),
+                       ("hit_sum", kt.PROFILE_HIT_SUM)):
         nl, ms, tasks, _ = kt.ktruss_profile_read(kind)
         if nl:
             kinds[name] = {"launches": nl, "ms": ms, "tasks": tasks}

@@ -226,14 +226,16 @@ int32_t ktruss_set_schedule(ktruss_graph* g, int32_t mode, const float* mlp_para
  *      per alive edge (its column, its row, one read and one write of its
  *      support word) plus 4 per row pointer;
  *   1  thread-per-edge launches, 2 wavefront-per-edge launches, 3 hub-row
- *      launches (tasks = edge tasks, or hub items for kind 3).
+ *      launches (tasks = edge tasks, or hub items for kind 3);
+ *   4  the row-local sum that adds the hub kernel's per-task hit words to
+ *      S(i, w) (tasks = alive edges).
  * Enabling (or disabling) clears the tallies.  Returns KTRUSS_OK.
  */
 int32_t ktruss_profile_enable(int32_t on);
 /*
  * Reads the tallies of `kind` since the last enable: launches, summed time in
  * milliseconds (synchronises on the recorded events), tasks and compulsory
- * bytes.  Any out pointer may be NULL.  E_INVALID for a kind outside 0..3.
+ * bytes.  Any out pointer may be NULL.  E_INVALID for a kind outside 0..4.
  */
 int32_t ktruss_profile_read(int32_t kind, int64_t* launches, double* total_ms, int64_t* tasks, int64_t* bytes);
 

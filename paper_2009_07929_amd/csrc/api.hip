@@ -85,6 +85,8 @@ FullLayout full_layout(int32_t n, int64_t m, int32_t G) {
     L.chunk_sz = take(vn);
     L.rs_hist = take(sizeof(int32_t) * (256 * (((size_t)m + kRsTile - 1) / kRsTile) + 1));
     L.is_hub = take((size_t)n + 1);
+    L.hub_row = take((size_t)n + 1);
+    L.hitw = take(sizeof(unsigned long long) * kHitWords * (size_t)m);
     L.wave_tasks = take(em);
     L.thread_tasks = take(em);
     L.ctl = take(sizeof(Ctl));
@@ -140,6 +142,8 @@ Work carve(void* work, int32_t n, int64_t m, int32_t G) {
     w.sc.chunk_sz = (int32_t*)(base + L.chunk_sz);
     w.sc.rs_hist = (int32_t*)(base + L.rs_hist);
     w.sc.is_hub = (uint8_t*)(base + L.is_hub);
+    w.sc.hub_row = (uint8_t*)(base + L.hub_row);
+    w.sc.hitw = (unsigned long long*)(base + L.hitw);
     w.sc.wave_tasks = (int32_t*)(base + L.wave_tasks);
     w.sc.thread_tasks = (int32_t*)(base + L.thread_tasks);
     w.ctl = (Ctl*)(base + L.ctl);
@@ -206,8 +210,9 @@ int32_t validate_on_device(const int32_t* rowptr, const int32_t* col, int32_t n,
 }
 
 // ---- profiling tallies (process-wide; guarded by a mutex)
-// kinds: 0 whole support pass, 1 thread-per-edge, 2 wavefront-per-edge, 3 hub
-constexpr int kKinds = 4;
+// kinds: 0 whole support pass, 1 thread-per-edge, 2 wavefront-per-edge, 3 hub,
+// 4 row-local sum of the hub hit words
+constexpr int kKinds = 5;
 struct Rec {
     int kind;
     hipEvent_t e0, e1;
@@ -315,6 +320,8 @@ int32_t support_pass(int sched, int32_t n, const Work& w, int p, const PassDims&
         rc = timed_launch(3, dm.items, s, [&] {
             return launch_support_hub(x, w.c[p], w.sc, dm.items, w.ctl, cycles, s);
         });
+        if (rc == KTRUSS_OK && dm.items > 0)
+            rc = timed_launch(4, dm.m, s, [&] { return launch_hit_sum(x, w.sc, &w.ctl->m_buf[p], dm.m, w.ctl, s); });
         if (rc == KTRUSS_OK && sched != KTRUSS_SCHED_FORCE_HUB) {
             rc = timed_launch(2, dm.n_wave, s, [&] {
                 return launch_support_wave(x, w.sc.wave_tasks, &w.ctl->n_wave, dm.n_wave, w.ctl, s);

@@ -16,6 +16,7 @@ constexpr int kScanThreads = 1024;
 // workgroup-per-hub-row kernel
 constexpr int kHubThreads = 256;     // 4 waves
 constexpr int kHubChunk = 256;       // tasks (in-edges of one row kappa) per hub item
+constexpr int kHubUnroll = 4;        // tail chunks whose loads a hub wave issues together
 constexpr int kSpanCap = 32768;      // widest label span staged as a rank bitmap
 constexpr int kSpanWords = kSpanCap / 32;
 constexpr int kKeyCap = 2 * kSpanWords;  // longest row kappa staged in LDS (keys / accumulators)
@@ -23,6 +24,7 @@ constexpr int kHubMaxGrid = 256 * 8;     // persistent hub grid: 8 workgroups pe
 constexpr int kStreamMaxGrid = 256 * 16; // grid-stride cap of the thread/wave task kernels
 constexpr int kMlpGradMaxBlocks = 512;   // workgroups of the cost-model gradient kernel
 constexpr int kRsTile = 4096;            // (column, edge) pairs per workgroup of the radix-sort transpose
+constexpr int kHitWords = 8;             // 64-bit hit words per task: tail offsets below 512 (see k_support_hub)
 
 // learned schedule defaults (predicted log2 shader cycles of a row's hub work)
 constexpr float kDefaultLearnedHubMin = 16.0f;
@@ -91,6 +93,8 @@ struct Scratch {
     int32_t* chunk_sz;    // int32[n]
     int32_t* rs_hist;     // int32[256 * ceil(m / kRsTile) + 1]: radix-sort digit histograms
     uint8_t* is_hub;      // uint8[n]
+    uint8_t* hub_row;     // uint8[n]: row kappa has hub items in the current pass
+    unsigned long long* hitw;  // uint64[kHitWords * m]: hub hit words, task-major
     int32_t* wave_tasks;  // int32[m]
     int32_t* thread_tasks;// int32[m]
 };
@@ -111,7 +115,8 @@ struct Layout {
     size_t col[2], src[2], eid[2], S[2], rowptr[2];
     size_t cedge[2], cptr[2];
     size_t xscan, cxscan, blockcnt, blockoff, blockcnt2, blockoff2, tmp_n, itemoff, item_kappa, item_c0, item_c1,
-        is_hub, wave_tasks, thread_tasks, insum, cycles, act_off, act_list, feats, pred, chunk_sz, rs_hist;
+        is_hub, hub_row, hitw, wave_tasks, thread_tasks, insum, cycles, act_off, act_list, feats, pred, chunk_sz,
+        rs_hist;
     size_t ctl;        // Ctl
     size_t total;
 };

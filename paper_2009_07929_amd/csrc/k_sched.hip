@@ -213,12 +213,14 @@ struct HubChunks {
 
 __global__ __launch_bounds__(kBlock) void k_hub_items(HubChunks f, int32_t n, const int32_t* __restrict__ itemoff,
                                                     int32_t* __restrict__ item_kappa, int32_t* __restrict__ item_c0,
-                                                    int32_t* __restrict__ item_c1, const Ctl* __restrict__ ctl) {
+                                                    int32_t* __restrict__ item_c1, uint8_t* __restrict__ hub_row,
+                                                    const Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k == 0) const_cast<Ctl*>(ctl)->item_next = 0;
     if (k >= n) return;
     const int32_t nch = f((int32_t)k);
+    hub_row[k] = nch > 0 ? 1 : 0;
     if (nch == 0) return;
     const int32_t o = itemoff[k];
     const int32_t c0 = f.cptr[k], cend = f.cptr[k + 1];
@@ -543,7 +545,8 @@ hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched,
     chunk_all = max(kMinLearnedChunk, min(chunk_all, kHubChunk));  // item capacity assumes >= kMinLearnedChunk
     HubChunks hc{x.rowptr, c.ptr, is_hub, chunk, chunk_all};
     device_scan(hc, n, ctl, sc, sc.itemoff, &ctl->n_items, s);
-    k_hub_items<<<grid_for(n), kBlock, 0, s>>>(hc, n, sc.itemoff, sc.item_kappa, sc.item_c0, sc.item_c1, ctl);
+    k_hub_items<<<grid_for(n), kBlock, 0, s>>>(hc, n, sc.itemoff, sc.item_kappa, sc.item_c0, sc.item_c1, sc.hub_row,
+                                               ctl);
     if (is_hub) {
         const int32_t wave_min = t.wave_min_work > 0 ? t.wave_min_work : kDefaultWaveMin;
         TaskClass tc{x, c, is_hub, wave_min};

@@ -112,13 +112,17 @@ __device__ __forceinline__ void wave_task(const Buf& x, int32_t e) {
 // tasks that select it.  Row kappa is staged once in LDS as a rank bitmap over
 // its label span (membership and position of a label with one 64-bit LDS
 // read), or as a sorted key array when the span is wide; its supports
-// S(kappa, :) accumulate in LDS and are flushed once per item.  Each wave takes
-// whole tasks and walks their tails (contiguous, coalesced reads).
+// S(kappa, :) accumulate in LDS and are flushed once per item.  Each wave walks
+// the tails of its tasks (contiguous, coalesced reads).  The hits of a task's
+// tail chunk, which belong to edges (i, w) of other rows' items, are stored as
+// one 64-bit word instead of one global atomic per triangle; k_hit_sum adds
+// them to S(i, w) row by row after the pass.
 enum { kModeBitmap = 0, kModeKeys = 1, kModeGlobal = 2 };
 
 __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const int32_t* __restrict__ item_kappa,
                                                            const int32_t* __restrict__ item_c0,
                                                            const int32_t* __restrict__ item_c1, Ctl* ctl,
+                                                           unsigned long long* __restrict__ hitw,
                                                            unsigned long long* __restrict__ cycles) {
     __shared__ uint2 s_bm[kSpanWords];   // rank bitmap {bits, set bits before this word}; or keys
     __shared__ int32_t s_acc[kKeyCap];
@@ -180,17 +184,52 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
             for (int32_t q = t; q < d; q += kHubThreads) s_acc[q] = 0;
         __syncthreads();
 
+        // Each wave walks the 64-element chunks of its tasks (kk = wv, wv + 4,
+        // ...) in order, kHubUnroll chunks per step: their loads are issued
+        // together, so several tail reads are in flight per wave however
+        // short the tails are.
         const int wv = t >> 6, lane = t & 63;
-        for (int32_t kk = wv; kk < ntask; kk += kHubThreads / 64) {
-            const int32_t e = s_e[kk], L = s_tl[kk], base = e + 1;
-            int cnt = 0;
-            for (int32_t o = 0; o < L; o += 64) {
-                const bool in = o + lane < L;
-                const int32_t pos = base + o + lane;
-                const int32_t w = in ? col[pos] : INT32_MAX;
-                const bool cand = in && w <= last;
-                if (__ballot(cand) == 0) break;  // ascending tail: the rest lies beyond row kappa
-                if (cand) {
+        int32_t kk = wv, ch = 0, e_cur = 0, L_cur = 0;
+        auto next_task = [&]() {
+            while (kk < ntask && s_tl[kk] <= 0) kk += kHubThreads / 64;
+            if (kk < ntask) {
+                e_cur = s_e[kk];
+                L_cur = s_tl[kk];
+            }
+        };
+        next_task();
+        uint32_t acc = 0;  // hits of the current task so far: S(i, kappa)
+        while (kk < ntask) {
+            int32_t ue[kHubUnroll], uc[kHubUnroll], uL[kHubUnroll], uw[kHubUnroll];
+            bool uv[kHubUnroll], ulast[kHubUnroll];
+#pragma unroll
+            for (int u = 0; u < kHubUnroll; ++u) {
+                uv[u] = kk < ntask;
+                ue[u] = e_cur;
+                uc[u] = ch;
+                uL[u] = L_cur;
+                ulast[u] = (ch + 1) * 64 >= L_cur;
+                if (uv[u]) {
+                    if (ulast[u]) {
+                        ch = 0;
+                        kk += kHubThreads / 64;
+                        next_task();
+                    } else {
+                        ++ch;
+                    }
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < kHubUnroll; ++u) {
+                const int32_t o = uc[u] * 64 + lane;
+                uw[u] = (uv[u] && o < uL[u]) ? col[ue[u] + 1 + o] : INT32_MAX;
+            }
+#pragma unroll
+            for (int u = 0; u < kHubUnroll; ++u) {
+                if (!uv[u]) continue;
+                const int32_t w = uw[u];
+                bool hit = false;
+                if (w <= last) {  // beyond the last label of row kappa nothing matches
                     int32_t q = -1;
                     if (mode == kModeBitmap) {
                         const int32_t off = w - k - 1;
@@ -205,15 +244,25 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
                         if (col[rs + qq] == w) q = qq;
                     }
                     if (q >= 0) {
-                        atomicAdd(&x.S[pos], 1);
+                        hit = true;
                         if (mode != kModeGlobal) atomicAdd(&s_acc[q], 1);
                         else atomicAdd(&x.S[rs + q], 1);
-                        ++cnt;
                     }
                 }
+                // S(i, w): the chunk's hits as one word, summed per row by
+                // k_hit_sum; chunks past kHitWords add directly.
+                const unsigned long long hb = __ballot(hit);
+                if (uc[u] < kHitWords) {
+                    if (lane == 0) hitw[(size_t)ue[u] * kHitWords + uc[u]] = hb;
+                } else if (hit) {
+                    atomicAdd(&x.S[ue[u] + 1 + uc[u] * 64 + lane], 1);
+                }
+                acc += (uint32_t)__popcll(hb);
+                if (ulast[u]) {
+                    if (lane == 0 && acc) atomicAdd(&x.S[ue[u]], (int32_t)acc);
+                    acc = 0;
+                }
             }
-            cnt = wave_sum(cnt);
-            if (lane == 0 && cnt) atomicAdd(&x.S[e], cnt);
         }
         __syncthreads();
         if (mode != kModeGlobal)
@@ -225,6 +274,30 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
             __syncthreads();
             if (t == 0) atomicAdd(&cycles[k], (unsigned long long)clock64() - t_start);
         }
+    }
+}
+
+// Row-local sum of the hub kernel's hit words: S(i, w) of the edge at
+// position p of row i gains one for every earlier task j of row i (a hub task,
+// hub_row[col[j]]) whose hit word has the bit of tail offset p - j - 1.  One
+// thread per edge; the threads of a row walk the same tasks in step, so the
+// task's column, flag and word are shared loads.
+__global__ __launch_bounds__(kBlock) void k_hit_sum(Buf x, const unsigned long long* __restrict__ hitw,
+                                                  const uint8_t* __restrict__ hub_row,
+                                                  const int32_t* __restrict__ count, const Ctl* __restrict__ ctl) {
+    if (ctl->done) return;
+    const int32_t m = *count;
+    const int32_t* __restrict__ col = x.col;
+    for (int32_t p = (int32_t)(blockIdx.x * kBlock + threadIdx.x); p < m; p += (int32_t)(gridDim.x * kBlock)) {
+        const int32_t rs = x.rowptr[x.src[p]];
+        int32_t add = 0;
+#pragma unroll 4
+        for (int32_t j = rs; j < p; ++j) {
+            const int32_t off = p - j - 1;  // tail offset of p in task j
+            if (off < kHitWords * 64 && hub_row[col[j]])
+                add += (int32_t)((hitw[(size_t)j * kHitWords + (off >> 6)] >> (off & 63)) & 1ull);
+        }
+        if (add) x.S[p] += add;
     }
 }
 
@@ -248,7 +321,14 @@ hipError_t launch_support_hub(const Buf& x, const Csc& c, const Scratch& sc, int
                               unsigned long long* cycles, hipStream_t s) {
     if (n_items_hint <= 0) return hipSuccess;
     k_support_hub<<<min(n_items_hint, kHubMaxGrid), kHubThreads, 0, s>>>(x, c, sc.item_kappa, sc.item_c0, sc.item_c1,
-                                                                        ctl, cycles);
+                                                                        ctl, sc.hitw, cycles);
+    return hipGetLastError();
+}
+
+hipError_t launch_hit_sum(const Buf& x, const Scratch& sc, const int32_t* m_count, int32_t m_hint, const Ctl* ctl,
+                          hipStream_t s) {
+    if (m_hint <= 0) return hipSuccess;
+    k_hit_sum<<<min(grid_for(m_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, sc.hitw, sc.hub_row, m_count, ctl);
     return hipGetLastError();
 }
 

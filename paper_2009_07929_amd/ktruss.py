@@ -199,7 +199,7 @@ def ktruss_profile_enable(on: bool = True):
     _check(load().ktruss_profile_enable(1 if on else 0))
 
 
-PROFILE_PASS, PROFILE_THREAD, PROFILE_WAVE, PROFILE_HUB = 0, 1, 2, 3
+PROFILE_PASS, PROFILE_THREAD, PROFILE_WAVE, PROFILE_HUB, PROFILE_HIT_SUM = 0, 1, 2, 3, 4
 
 
 def ktruss_profile_read(kind: int = PROFILE_PASS):
