@@ -63,6 +63,7 @@ FullLayout full_layout(int32_t n, int64_t m, int32_t G) {
         L.S[b] = take(em);
         L.rowptr[b] = take(vn);
         L.cedge[b] = take(em);
+        L.csrc[b] = take(em);
         L.cptr[b] = take(vn);
     }
     L.xscan = take(em1);
@@ -73,9 +74,8 @@ FullLayout full_layout(int32_t n, int64_t m, int32_t G) {
     L.blockoff2 = take(sizeof(int32_t) * 2 * kMaxScanBlocks);
     L.tmp_n = take(vn);
     L.itemoff = take(vn);
-    L.item_kappa = take(sizeof(int32_t) * (size_t)item_capacity(n, m));
-    L.item_c0 = take(sizeof(int32_t) * (size_t)item_capacity(n, m));
-    L.item_c1 = take(sizeof(int32_t) * (size_t)item_capacity(n, m));
+    L.items = take(sizeof(HubItem) * (size_t)item_capacity(n, m));
+    L.ctail = take(em);
     L.insum = take(sizeof(unsigned long long) * ((size_t)n + 1));
     L.cycles = take(sizeof(unsigned long long) * ((size_t)n + 1));
     L.act_off = take(vn);
@@ -120,6 +120,7 @@ Work carve(void* work, int32_t n, int64_t m, int32_t G) {
         w.b[b].S = (int32_t*)(base + L.S[b]);
         w.b[b].rowptr = (int32_t*)(base + L.rowptr[b]);
         w.c[b].edge = (int32_t*)(base + L.cedge[b]);
+        w.c[b].src = (int32_t*)(base + L.csrc[b]);
         w.c[b].ptr = (int32_t*)(base + L.cptr[b]);
     }
     w.sc.xscan = (int32_t*)(base + L.xscan);
@@ -130,9 +131,8 @@ Work carve(void* work, int32_t n, int64_t m, int32_t G) {
     w.sc.blockoff2 = (int32_t*)(base + L.blockoff2);
     w.sc.tmp_n = (int32_t*)(base + L.tmp_n);
     w.sc.itemoff = (int32_t*)(base + L.itemoff);
-    w.sc.item_kappa = (int32_t*)(base + L.item_kappa);
-    w.sc.item_c0 = (int32_t*)(base + L.item_c0);
-    w.sc.item_c1 = (int32_t*)(base + L.item_c1);
+    w.sc.items = (HubItem*)(base + L.items);
+    w.sc.ctail = (int32_t*)(base + L.ctail);
     w.sc.insum = (unsigned long long*)(base + L.insum);
     w.sc.cycles = (unsigned long long*)(base + L.cycles);
     w.sc.act_off = (int32_t*)(base + L.act_off);
@@ -321,7 +321,7 @@ int32_t support_pass(int sched, int32_t n, const Work& w, int p, const PassDims&
             return launch_support_hub(x, w.c[p], w.sc, dm.items, w.ctl, cycles, s);
         });
         if (rc == KTRUSS_OK && dm.items > 0)
-            rc = timed_launch(4, dm.m, s, [&] { return launch_hit_sum(x, w.sc, &w.ctl->m_buf[p], dm.m, w.ctl, s); });
+            rc = timed_launch(4, dm.m, s, [&] { return launch_hit_sum(x, w.sc, n, w.ctl, s); });
         if (rc == KTRUSS_OK && sched != KTRUSS_SCHED_FORCE_HUB) {
             rc = timed_launch(2, dm.n_wave, s, [&] {
                 return launch_support_wave(x, w.sc.wave_tasks, &w.ctl->n_wave, dm.n_wave, w.ctl, s);

@@ -16,7 +16,7 @@ constexpr int kScanThreads = 1024;
 // workgroup-per-hub-row kernel
 constexpr int kHubThreads = 256;     // 4 waves
 constexpr int kHubChunk = 256;       // tasks (in-edges of one row kappa) per hub item
-constexpr int kHubUnroll = 4;        // tail chunks whose loads a hub wave issues together
+constexpr int kHubUnroll = 6;        // tail chunks whose loads a hub wave issues together
 constexpr int kSpanCap = 32768;      // widest label span staged as a rank bitmap
 constexpr int kSpanWords = kSpanCap / 32;
 constexpr int kKeyCap = 2 * kSpanWords;  // longest row kappa staged in LDS (keys / accumulators)
@@ -65,10 +65,17 @@ struct Buf {
 };
 
 // In-edge lists of a buffer: for every row kappa, the positions of the edges
-// whose column is kappa (edge[ptr[kappa] .. ptr[kappa+1])).
+// whose column is kappa (edge[ptr[kappa] .. ptr[kappa+1])) and their rows.
 struct Csc {
     int32_t* edge;
+    int32_t* src;
     int32_t* ptr;
+};
+
+// One hub item: row kappa (its first position rs, length d and last label)
+// and the in-edge list entries [c0, c1) of the tasks that select it.
+struct HubItem {
+    int32_t k, c0, c1, rs, d, last, pad0, pad1;
 };
 
 // Per-run scratch arrays inside the workspace.
@@ -81,9 +88,8 @@ struct Scratch {
     int32_t* blockoff2;   // int32[2*kMaxScanBlocks]
     int32_t* tmp_n;       // int32[n]
     int32_t* itemoff;     // int32[n+1]
-    int32_t* item_kappa;  // int32[item capacity]
-    int32_t* item_c0;     // int32[item capacity]
-    int32_t* item_c1;     // int32[item capacity]
+    HubItem* items;       // HubItem[item capacity]
+    int32_t* ctail;       // int32[m]: tail length of the task of every in-edge list entry
     unsigned long long* insum;   // uint64[n]: sum of in-neighbour out-degrees
     unsigned long long* cycles;  // uint64[n]: measured hub cycles per row (sampling)
     int32_t* act_off;     // int32[n+1]
@@ -113,8 +119,8 @@ struct BatchCtx {
 
 struct Layout {
     size_t col[2], src[2], eid[2], S[2], rowptr[2];
-    size_t cedge[2], cptr[2];
-    size_t xscan, cxscan, blockcnt, blockoff, blockcnt2, blockoff2, tmp_n, itemoff, item_kappa, item_c0, item_c1,
+    size_t cedge[2], csrc[2], cptr[2];
+    size_t xscan, cxscan, blockcnt, blockoff, blockcnt2, blockoff2, tmp_n, itemoff, items, ctail,
         is_hub, hub_row, hitw, wave_tasks, thread_tasks, insum, cycles, act_off, act_list, feats, pred, chunk_sz,
         rs_hist;
     size_t ctl;        // Ctl

@@ -75,7 +75,10 @@ struct CscEntry {
         return alive_can[x.eid[e]] != 0;
     }
     __device__ void drop(int32_t) const {}
-    __device__ void emit(int32_t c, int32_t q) const { cy.edge[q] = xscan[cx.edge[c]]; }
+    __device__ void emit(int32_t c, int32_t q) const {
+        cy.edge[q] = xscan[cx.edge[c]];
+        cy.src[q] = cx.src[c];
+    }
 };
 
 // ---- generic stable filter

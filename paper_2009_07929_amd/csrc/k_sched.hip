@@ -191,6 +191,23 @@ __global__ __launch_bounds__(kBlock) void k_col_ptr(const int32_t* __restrict__ 
     cptr[k] = lower_bound_i32(sorted, m, (int32_t)k);
 }
 
+// Row of every in-edge list entry (the edge's row i).
+__global__ __launch_bounds__(kBlock) void k_csc_rows(const int32_t* __restrict__ src, const int32_t* __restrict__ edge,
+                                                   int32_t m, int32_t* __restrict__ csrc) {
+    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (q < m) csrc[q] = src[edge[q]];
+}
+
+// Tail length of the task of every in-edge list entry of the pass: the part
+// of row i after the edge (Algorithm 3's a12(j+1:)).
+__global__ __launch_bounds__(kBlock) void k_task_tails(Buf x, Csc c, const Ctl* __restrict__ ctl, int p,
+                                                     int32_t* __restrict__ ctail) {
+    if (ctl->done) return;
+    const int32_t m = ctl->m_buf[p];
+    for (int32_t q = (int32_t)(blockIdx.x * kBlock + threadIdx.x); q < m; q += (int32_t)(gridDim.x * kBlock))
+        ctail[q] = x.rowptr[c.src[q] + 1] - c.edge[q] - 1;
+}
+
 // ---- hub items
 
 // Number of hub items of row kappa: its in-edges cut into chunks of kHubChunk.
@@ -211,10 +228,9 @@ struct HubChunks {
     }
 };
 
-__global__ __launch_bounds__(kBlock) void k_hub_items(HubChunks f, int32_t n, const int32_t* __restrict__ itemoff,
-                                                    int32_t* __restrict__ item_kappa, int32_t* __restrict__ item_c0,
-                                                    int32_t* __restrict__ item_c1, uint8_t* __restrict__ hub_row,
-                                                    const Ctl* __restrict__ ctl) {
+__global__ __launch_bounds__(kBlock) void k_hub_items(HubChunks f, const int32_t* __restrict__ col, int32_t n,
+                                                    const int32_t* __restrict__ itemoff, HubItem* __restrict__ items,
+                                                    uint8_t* __restrict__ hub_row, const Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k == 0) const_cast<Ctl*>(ctl)->item_next = 0;
@@ -225,10 +241,18 @@ __global__ __launch_bounds__(kBlock) void k_hub_items(HubChunks f, int32_t n, co
     const int32_t o = itemoff[k];
     const int32_t c0 = f.cptr[k], cend = f.cptr[k + 1];
     const int32_t cs = f.size((int32_t)k);
+    const int32_t rs = f.rowptr[k], d = f.rowptr[k + 1] - rs;
+    const int32_t last = col[rs + d - 1];
     for (int32_t j = 0; j < nch; ++j) {
-        item_kappa[o + j] = (int32_t)k;
-        item_c0[o + j] = c0 + j * cs;
-        item_c1[o + j] = min(c0 + (j + 1) * cs, cend);
+        HubItem h;
+        h.k = (int32_t)k;
+        h.c0 = c0 + j * cs;
+        h.c1 = min(c0 + (j + 1) * cs, cend);
+        h.rs = rs;
+        h.d = d;
+        h.last = last;
+        h.pad0 = h.pad1 = 0;
+        items[o + j] = h;
     }
 }
 
@@ -385,7 +409,7 @@ struct TaskClass {
         const int32_t e = c.edge[i];
         const int32_t k = x.col[e];
         if (is_hub[k]) return 0;
-        const int32_t tail = x.rowptr[x.src[e] + 1] - e - 1;
+        const int32_t tail = x.rowptr[c.src[i] + 1] - e - 1;
         const int32_t d = x.rowptr[k + 1] - x.rowptr[k];
         if (tail == 0 || d == 0) return 0;  // no triangle can close on this task
         return (tail + d >= wave_min) ? 1 : 2;
@@ -495,6 +519,7 @@ hipError_t launch_build_csc(const Buf& b, const Csc& c, int32_t n, int32_t m, Sc
         vin = vout;
     }
     k_col_ptr<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(kin, m, n, c.ptr);
+    k_csc_rows<<<grid_for(m), kBlock, 0, s>>>(b.src, c.edge, m, c.src);
     return hipGetLastError();
 }
 
@@ -545,8 +570,9 @@ hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched,
     chunk_all = max(kMinLearnedChunk, min(chunk_all, kHubChunk));  // item capacity assumes >= kMinLearnedChunk
     HubChunks hc{x.rowptr, c.ptr, is_hub, chunk, chunk_all};
     device_scan(hc, n, ctl, sc, sc.itemoff, &ctl->n_items, s);
-    k_hub_items<<<grid_for(n), kBlock, 0, s>>>(hc, n, sc.itemoff, sc.item_kappa, sc.item_c0, sc.item_c1, sc.hub_row,
-                                               ctl);
+    k_hub_items<<<grid_for(n), kBlock, 0, s>>>(hc, x.col, n, sc.itemoff, sc.items, sc.hub_row, ctl);
+    if (m_hint > 0)
+        k_task_tails<<<min(grid_for(m_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, c, ctl, p, sc.ctail);
     if (is_hub) {
         const int32_t wave_min = t.wave_min_work > 0 ? t.wave_min_work : kDefaultWaveMin;
         TaskClass tc{x, c, is_hub, wave_min};

@@ -119,9 +119,127 @@ __device__ __forceinline__ void wave_task(const Buf& x, int32_t e) {
 // them to S(i, w) row by row after the pass.
 enum { kModeBitmap = 0, kModeKeys = 1, kModeGlobal = 2 };
 
-__global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const int32_t* __restrict__ item_kappa,
-                                                           const int32_t* __restrict__ item_c0,
-                                                           const int32_t* __restrict__ item_c1, Ctl* ctl,
+// The task loop of one hub item, for one wave.  The wave walks the 64-element
+// chunks of its tasks (kk = wave, wave + 4, ...) in order, kHubUnroll chunks
+// per step.  A step issues the tail loads of all its chunks, then does their
+// lookups (LDS), then writes their hit words and finished task counts with one
+// store and one atomic instruction (lane u carries chunk u): stores never sit
+// between a load and its use, so the wave waits for memory once per step.
+template <int MODE>
+__device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __restrict__ hitw,
+                                          const int32_t* s_e, const int32_t* s_tl, int32_t ntask, int32_t k,
+                                          int32_t rs, int32_t d, int32_t last, const uint2* s_bm, int32_t* s_acc) {
+    const int32_t* __restrict__ col = x.col;
+    const int32_t* s_keys = reinterpret_cast<const int32_t*>(s_bm);
+    const int lane = (int)(threadIdx.x & 63);
+    constexpr int kWaves = kHubThreads / 64;
+    int32_t kk = (int32_t)(threadIdx.x >> 6), ch = 0, e_cur = 0, L_cur = 0;
+    auto next_task = [&]() {  // skip tasks with an empty tail
+        while (kk < ntask) {
+            const int32_t L = __builtin_amdgcn_readfirstlane(s_tl[kk]);
+            if (L > 0) {
+                L_cur = L;
+                e_cur = __builtin_amdgcn_readfirstlane(s_e[kk]);
+                return;
+            }
+            kk += kWaves;
+        }
+    };
+    next_task();
+    int32_t acc = 0;  // hits of the current task so far: S(i, kappa)
+    while (kk < ntask) {
+        int32_t ue[kHubUnroll], uc[kHubUnroll], uL[kHubUnroll];
+        bool uv[kHubUnroll], ulast[kHubUnroll];
+#pragma unroll
+        for (int u = 0; u < kHubUnroll; ++u) {
+            uv[u] = kk < ntask;
+            ue[u] = e_cur;
+            uc[u] = ch;
+            uL[u] = L_cur;
+            ulast[u] = (ch + 1) * 64 >= L_cur;
+            if (uv[u]) {
+                if (ulast[u]) {
+                    ch = 0;
+                    kk += kWaves;
+                    next_task();
+                } else {
+                    ++ch;
+                }
+            }
+        }
+        // unconditional loads (lanes past the tail read the task's own edge),
+        // so that the compiler can wait for them one at a time
+        int32_t uw[kHubUnroll];
+        bool uin[kHubUnroll];
+#pragma unroll
+        for (int u = 0; u < kHubUnroll; ++u) {
+            const int32_t o = uc[u] * 64 + lane;
+            uin[u] = uv[u] && o < uL[u];
+            uw[u] = col[uin[u] ? ue[u] + 1 + o : ue[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < kHubUnroll; ++u)
+            if (!uin[u]) uw[u] = INT32_MAX;
+        unsigned long long hb[kHubUnroll];
+#pragma unroll
+        for (int u = 0; u < kHubUnroll; ++u) {
+            const int32_t w = uw[u];
+            bool hit = false;
+            if (w <= last) {  // beyond the last label of row kappa nothing matches
+                int32_t q = -1;
+                if (MODE == kModeBitmap) {
+                    const int32_t off = w - k - 1;
+                    const uint2 bw = s_bm[off >> 5];
+                    const uint32_t bit = (uint32_t)off & 31u;
+                    if ((bw.x >> bit) & 1u) q = (int32_t)(bw.y + __popc(bw.x & ((1u << bit) - 1u)));
+                } else if (MODE == kModeKeys) {
+                    const int32_t qq = lower_bound_i32(s_keys, d, w);
+                    if (s_keys[qq] == w) q = qq;
+                } else {
+                    const int32_t qq = lower_bound_i32(col + rs, d, w);
+                    if (col[rs + qq] == w) q = qq;
+                }
+                if (q >= 0) {
+                    hit = true;
+                    if (MODE != kModeGlobal) atomicAdd(&s_acc[q], 1);
+                    else atomicAdd(&x.S[rs + q], 1);
+                }
+            }
+            hb[u] = __ballot(hit);
+        }
+        // S(i, w) of chunks past kHitWords (tails longer than 64 * kHitWords),
+        // after the lookups so that no memory operation sits among them
+#pragma unroll
+        for (int u = 0; u < kHubUnroll; ++u)
+            if (uv[u] && uc[u] >= kHitWords && ((hb[u] >> lane) & 1ull))
+                atomicAdd(&x.S[ue[u] + 1 + uc[u] * 64 + lane], 1);
+        // lane u: hit word of chunk u, and the count of the task that chunk u ends
+        unsigned long long my_word = 0;
+        int64_t my_word_at = -1;
+        int32_t my_cnt = 0, my_cnt_at = -1;
+#pragma unroll
+        for (int u = 0; u < kHubUnroll; ++u) {
+            if (!uv[u]) continue;
+            acc += __popcll(hb[u]);
+            if (lane == u && uc[u] < kHitWords) {
+                my_word = hb[u];
+                my_word_at = (int64_t)ue[u] * kHitWords + uc[u];
+            }
+            if (ulast[u]) {
+                if (lane == u && acc) {
+                    my_cnt = acc;
+                    my_cnt_at = ue[u];
+                }
+                acc = 0;
+            }
+        }
+        if (my_word_at >= 0) hitw[my_word_at] = my_word;
+        if (my_cnt_at >= 0) atomicAdd(&x.S[my_cnt_at], my_cnt);
+    }
+}
+
+__global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const HubItem* __restrict__ items,
+                                                           const int32_t* __restrict__ ctail, Ctl* ctl,
                                                            unsigned long long* __restrict__ hitw,
                                                            unsigned long long* __restrict__ cycles) {
     __shared__ uint2 s_bm[kSpanWords];   // rank bitmap {bits, set bits before this word}; or keys
@@ -132,29 +250,27 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
     __shared__ int32_t s_it;
     if (ctl->done) return;
     const int32_t n_items = ctl->n_items;
+    const int t = threadIdx.x;
     // Persistent: workgroups pull items from a device counter.  Items are laid
     // out by ascending kappa and the heaviest rows carry the largest labels, so
-    // they are taken from the end first (longest work first).
+    // they are taken from the end first (longest work first).  The ticket of
+    // the next item is requested while the current one is processed.
+    if (t == 0) s_it = atomicAdd(&ctl->item_next, 1);
+    __syncthreads();
     for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_it = atomicAdd(&ctl->item_next, 1);
-        __syncthreads();
         const int32_t it = n_items - 1 - s_it;
         if (it < 0) break;
+        int32_t ticket = 0;
+        if (t == 0) ticket = atomicAdd(&ctl->item_next, 1);
         const int32_t* __restrict__ col = x.col;
-        const int32_t k = item_kappa[it];
-        const int32_t c0 = item_c0[it];
-        const int32_t c1 = item_c1[it];
+        const HubItem h = items[it];
+        const int32_t k = h.k, c0 = h.c0, rs = h.rs, d = h.d, last = h.last;
         const unsigned long long t_start = cycles ? (unsigned long long)clock64() : 0ull;
-        const int32_t ntask = c1 - c0;
-        const int32_t rs = x.rowptr[k], d = x.rowptr[k + 1] - rs;
-        const int t = threadIdx.x;
+        const int32_t ntask = h.c1 - c0;
         if (t < ntask) {
-            const int32_t e = c.edge[c0 + t];
-            s_e[t] = e;
-            s_tl[t] = x.rowptr[x.src[e] + 1] - e - 1;
+            s_e[t] = c.edge[c0 + t];
+            s_tl[t] = ctail[c0 + t];
         }
-        const int32_t last = col[rs + d - 1];
         const int32_t span = last - k;  // labels of row kappa lie in (k, last]
         const int mode = d > kKeyCap ? kModeGlobal : (span <= kSpanCap ? kModeBitmap : kModeKeys);
         int32_t* s_keys = reinterpret_cast<int32_t*>(s_bm);
@@ -184,86 +300,12 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
             for (int32_t q = t; q < d; q += kHubThreads) s_acc[q] = 0;
         __syncthreads();
 
-        // Each wave walks the 64-element chunks of its tasks (kk = wv, wv + 4,
-        // ...) in order, kHubUnroll chunks per step: their loads are issued
-        // together, so several tail reads are in flight per wave however
-        // short the tails are.
-        const int wv = t >> 6, lane = t & 63;
-        int32_t kk = wv, ch = 0, e_cur = 0, L_cur = 0;
-        auto next_task = [&]() {
-            while (kk < ntask && s_tl[kk] <= 0) kk += kHubThreads / 64;
-            if (kk < ntask) {
-                e_cur = s_e[kk];
-                L_cur = s_tl[kk];
-            }
-        };
-        next_task();
-        uint32_t acc = 0;  // hits of the current task so far: S(i, kappa)
-        while (kk < ntask) {
-            int32_t ue[kHubUnroll], uc[kHubUnroll], uL[kHubUnroll], uw[kHubUnroll];
-            bool uv[kHubUnroll], ulast[kHubUnroll];
-#pragma unroll
-            for (int u = 0; u < kHubUnroll; ++u) {
-                uv[u] = kk < ntask;
-                ue[u] = e_cur;
-                uc[u] = ch;
-                uL[u] = L_cur;
-                ulast[u] = (ch + 1) * 64 >= L_cur;
-                if (uv[u]) {
-                    if (ulast[u]) {
-                        ch = 0;
-                        kk += kHubThreads / 64;
-                        next_task();
-                    } else {
-                        ++ch;
-                    }
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < kHubUnroll; ++u) {
-                const int32_t o = uc[u] * 64 + lane;
-                uw[u] = (uv[u] && o < uL[u]) ? col[ue[u] + 1 + o] : INT32_MAX;
-            }
-#pragma unroll
-            for (int u = 0; u < kHubUnroll; ++u) {
-                if (!uv[u]) continue;
-                const int32_t w = uw[u];
-                bool hit = false;
-                if (w <= last) {  // beyond the last label of row kappa nothing matches
-                    int32_t q = -1;
-                    if (mode == kModeBitmap) {
-                        const int32_t off = w - k - 1;
-                        const uint2 bw = s_bm[off >> 5];
-                        const uint32_t bit = (uint32_t)off & 31u;
-                        if ((bw.x >> bit) & 1u) q = (int32_t)(bw.y + __popc(bw.x & ((1u << bit) - 1u)));
-                    } else if (mode == kModeKeys) {
-                        const int32_t qq = lower_bound_i32(s_keys, d, w);
-                        if (s_keys[qq] == w) q = qq;
-                    } else {
-                        const int32_t qq = lower_bound_i32(col + rs, d, w);
-                        if (col[rs + qq] == w) q = qq;
-                    }
-                    if (q >= 0) {
-                        hit = true;
-                        if (mode != kModeGlobal) atomicAdd(&s_acc[q], 1);
-                        else atomicAdd(&x.S[rs + q], 1);
-                    }
-                }
-                // S(i, w): the chunk's hits as one word, summed per row by
-                // k_hit_sum; chunks past kHitWords add directly.
-                const unsigned long long hb = __ballot(hit);
-                if (uc[u] < kHitWords) {
-                    if (lane == 0) hitw[(size_t)ue[u] * kHitWords + uc[u]] = hb;
-                } else if (hit) {
-                    atomicAdd(&x.S[ue[u] + 1 + uc[u] * 64 + lane], 1);
-                }
-                acc += (uint32_t)__popcll(hb);
-                if (ulast[u]) {
-                    if (lane == 0 && acc) atomicAdd(&x.S[ue[u]], (int32_t)acc);
-                    acc = 0;
-                }
-            }
-        }
+        if (mode == kModeBitmap)
+            hub_tasks<kModeBitmap>(x, hitw, s_e, s_tl, ntask, k, rs, d, last, s_bm, s_acc);
+        else if (mode == kModeKeys)
+            hub_tasks<kModeKeys>(x, hitw, s_e, s_tl, ntask, k, rs, d, last, s_bm, s_acc);
+        else
+            hub_tasks<kModeGlobal>(x, hitw, s_e, s_tl, ntask, k, rs, d, last, s_bm, s_acc);
         __syncthreads();
         if (mode != kModeGlobal)
             for (int32_t q = t; q < d; q += kHubThreads) {
@@ -274,30 +316,71 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
             __syncthreads();
             if (t == 0) atomicAdd(&cycles[k], (unsigned long long)clock64() - t_start);
         }
+        __syncthreads();  // every thread has read s_it and the item's LDS
+        if (t == 0) s_it = ticket;
+        __syncthreads();
     }
 }
 
+// 64x64 bit transpose across a wave: lane j holds row j (bit l = entry
+// (j, l)); afterwards lane l holds column l (bit j = entry (j, l)).  Six
+// butterfly stages swap the off-diagonal blocks of halving size.
+__device__ __forceinline__ unsigned long long transpose64(unsigned long long v, int lane) {
+    const unsigned long long keep[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                                        0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+    for (int st = 0; st < 6; ++st) {
+        const int b = 32 >> st;
+        const unsigned long long m = keep[st];
+        const uint32_t lo = __shfl_xor((uint32_t)v, b), hi = __shfl_xor((uint32_t)(v >> 32), b);
+        const unsigned long long y = ((unsigned long long)hi << 32) | lo;
+        v = (lane & b) ? ((v & ~m) | ((y & ~m) >> b)) : ((v & m) | ((y & m) << b));
+    }
+    return v;
+}
+
 // Row-local sum of the hub kernel's hit words: S(i, w) of the edge at
-// position p of row i gains one for every earlier task j of row i (a hub task,
-// hub_row[col[j]]) whose hit word has the bit of tail offset p - j - 1.  One
-// thread per edge; the threads of a row walk the same tasks in step, so the
-// task's column, flag and word are shared loads.
+// position p of row i gains one for every earlier task j of row i (a hub task:
+// hub_row[col[j]]) whose hit words have the bit of tail offset p - j - 1.
+// One wave per row, 64 positions at a time: each lane takes a task, aligns the
+// task's words to the 64 positions (a funnel shift of two words), and a bit
+// transpose plus popcount turns the 64 aligned words into 64 per-position
+// counts.  Only tasks within kHitWords words of the block have words.
 __global__ __launch_bounds__(kBlock) void k_hit_sum(Buf x, const unsigned long long* __restrict__ hitw,
-                                                  const uint8_t* __restrict__ hub_row,
-                                                  const int32_t* __restrict__ count, const Ctl* __restrict__ ctl) {
+                                                  const uint8_t* __restrict__ hub_row, int32_t n,
+                                                  const Ctl* __restrict__ ctl) {
     if (ctl->done) return;
-    const int32_t m = *count;
+    const int lane = (int)(threadIdx.x & 63);
+    const int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (i >= n) return;
+    const int32_t rs = x.rowptr[i], d = x.rowptr[i + 1] - rs;
+    if (d < 2) return;
     const int32_t* __restrict__ col = x.col;
-    for (int32_t p = (int32_t)(blockIdx.x * kBlock + threadIdx.x); p < m; p += (int32_t)(gridDim.x * kBlock)) {
-        const int32_t rs = x.rowptr[x.src[p]];
-        int32_t add = 0;
-#pragma unroll 4
-        for (int32_t j = rs; j < p; ++j) {
-            const int32_t off = p - j - 1;  // tail offset of p in task j
-            if (off < kHitWords * 64 && hub_row[col[j]])
-                add += (int32_t)((hitw[(size_t)j * kHitWords + (off >> 6)] >> (off & 63)) & 1ull);
+    const int32_t nb = (d + 63) >> 6;
+    for (int32_t pb = 0; pb < nb; ++pb) {
+        const int32_t p0 = pb * 64;
+        uint32_t add = 0;
+        for (int32_t tb = max(0, pb - kHitWords); tb <= pb; ++tb) {
+            const int32_t j = tb * 64 + lane;  // this lane's task (row-local)
+            unsigned long long v = 0;
+            if (j < d - 1 && hub_row[col[rs + j]]) {
+                const unsigned long long* __restrict__ hw = hitw + (size_t)(rs + j) * kHitWords;
+                const int32_t L = d - 1 - j;   // tail length; words 0 .. ceil(L/64)-1 (below kHitWords) exist
+                const int32_t t0 = p0 - j - 1;  // tail offset of position p0
+                if (t0 < 0) {
+                    const int32_t sh = -t0;  // 1..64: position p0 + sh is tail offset 0
+                    v = sh < 64 ? (hw[0] << sh) : 0ull;
+                } else {
+                    const int32_t c = t0 >> 6, sft = t0 & 63;
+                    const unsigned long long lo = (c < kHitWords && c * 64 < L) ? hw[c] : 0ull;
+                    const unsigned long long hi = (c + 1 < kHitWords && (c + 1) * 64 < L) ? hw[c + 1] : 0ull;
+                    v = sft ? ((lo >> sft) | (hi << (64 - sft))) : lo;
+                }
+            }
+            add += (uint32_t)__popcll(transpose64(v, lane));
         }
-        if (add) x.S[p] += add;
+        const int32_t p = p0 + lane;
+        if (p < d && add) x.S[rs + p] += (int32_t)add;
     }
 }
 
@@ -320,15 +403,15 @@ hipError_t launch_support_wave(const Buf& x, const int32_t* tasks, const int32_t
 hipError_t launch_support_hub(const Buf& x, const Csc& c, const Scratch& sc, int32_t n_items_hint, Ctl* ctl,
                               unsigned long long* cycles, hipStream_t s) {
     if (n_items_hint <= 0) return hipSuccess;
-    k_support_hub<<<min(n_items_hint, kHubMaxGrid), kHubThreads, 0, s>>>(x, c, sc.item_kappa, sc.item_c0, sc.item_c1,
-                                                                        ctl, sc.hitw, cycles);
+    k_support_hub<<<min(n_items_hint, kHubMaxGrid), kHubThreads, 0, s>>>(x, c, sc.items, sc.ctail, ctl, sc.hitw,
+                                                                        cycles);
     return hipGetLastError();
 }
 
-hipError_t launch_hit_sum(const Buf& x, const Scratch& sc, const int32_t* m_count, int32_t m_hint, const Ctl* ctl,
-                          hipStream_t s) {
-    if (m_hint <= 0) return hipSuccess;
-    k_hit_sum<<<min(grid_for(m_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, sc.hitw, sc.hub_row, m_count, ctl);
+hipError_t launch_hit_sum(const Buf& x, const Scratch& sc, int32_t n, const Ctl* ctl, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)(((int64_t)n + kBlock / 64 - 1) / (kBlock / 64));  // one wave per row
+    k_hit_sum<<<grid, kBlock, 0, s>>>(x, sc.hitw, sc.hub_row, n, ctl);
     return hipGetLastError();
 }
 
