@@ -118,6 +118,7 @@ __device__ __forceinline__ void wave_task(const Buf& x, int32_t e) {
 // one 64-bit word instead of one global atomic per triangle; k_hit_sum adds
 // them to S(i, w) row by row after the pass.
 enum { kModeBitmap = 0, kModeKeys = 1, kModeGlobal = 2 };
+static_assert(kHubChunk <= kHubThreads, "each wave holds at most 64 of an item's tasks in registers");
 
 // The task loop of one hub item, for one wave.  The wave walks the 64-element
 // chunks of its tasks (kk = wave, wave + 4, ...) in order, kHubUnroll chunks
@@ -127,32 +128,43 @@ enum { kModeBitmap = 0, kModeKeys = 1, kModeGlobal = 2 };
 // between a load and its use, so the wave waits for memory once per step.
 template <int MODE>
 __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __restrict__ hitw,
-                                          const int32_t* s_e, const int32_t* s_tl, int32_t ntask, int32_t k,
-                                          int32_t rs, int32_t d, int32_t last, const uint2* s_bm, int32_t* s_acc) {
+                                          const int32_t* __restrict__ cedge, const int32_t* __restrict__ ctail,
+                                          int32_t c0, int32_t ntask, int32_t k, int32_t rs, int32_t d, int32_t last,
+                                          const uint2* s_bm, int32_t* s_acc) {
     const int32_t* __restrict__ col = x.col;
     const int32_t* s_keys = reinterpret_cast<const int32_t*>(s_bm);
     const int lane = (int)(threadIdx.x & 63);
+    const int32_t wv = (int32_t)(threadIdx.x >> 6);
     constexpr int kWaves = kHubThreads / 64;
-    int32_t kk = (int32_t)(threadIdx.x >> 6), ch = 0, e_cur = 0, L_cur = 0;
+    // this wave's tasks wv, wv + 4, ... (at most 64): lane r holds task r's
+    // edge and tail length; the walk reads them with readlane
+    const int32_t mine = wv + kWaves * lane;
+    int32_t t_e = 0, t_L = 0;
+    if (mine < ntask) {
+        t_e = cedge[c0 + mine];
+        t_L = ctail[c0 + mine];
+    }
+    const int32_t nmine = ntask > wv ? (ntask - wv + kWaves - 1) / kWaves : 0;
+    int32_t r = 0, ch = 0, e_cur = 0, L_cur = 0;
     auto next_task = [&]() {  // skip tasks with an empty tail
-        while (kk < ntask) {
-            const int32_t L = __builtin_amdgcn_readfirstlane(s_tl[kk]);
+        while (r < nmine) {
+            const int32_t L = __builtin_amdgcn_readlane(t_L, r);
             if (L > 0) {
                 L_cur = L;
-                e_cur = __builtin_amdgcn_readfirstlane(s_e[kk]);
+                e_cur = __builtin_amdgcn_readlane(t_e, r);
                 return;
             }
-            kk += kWaves;
+            ++r;
         }
     };
     next_task();
     int32_t acc = 0;  // hits of the current task so far: S(i, kappa)
-    while (kk < ntask) {
+    while (r < nmine) {
         int32_t ue[kHubUnroll], uc[kHubUnroll], uL[kHubUnroll];
         bool uv[kHubUnroll], ulast[kHubUnroll];
 #pragma unroll
         for (int u = 0; u < kHubUnroll; ++u) {
-            uv[u] = kk < ntask;
+            uv[u] = r < nmine;
             ue[u] = e_cur;
             uc[u] = ch;
             uL[u] = L_cur;
@@ -160,7 +172,7 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
             if (uv[u]) {
                 if (ulast[u]) {
                     ch = 0;
-                    kk += kWaves;
+                    ++r;
                     next_task();
                 } else {
                     ++ch;
@@ -181,31 +193,45 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
         for (int u = 0; u < kHubUnroll; ++u)
             if (!uin[u]) uw[u] = INT32_MAX;
         unsigned long long hb[kHubUnroll];
+        if (MODE == kModeBitmap) {
+            // all chunks' bitmap words first (independent LDS reads), then
+            // ranks and LDS accumulations
+            unsigned long long bw[kHubUnroll];
 #pragma unroll
-        for (int u = 0; u < kHubUnroll; ++u) {
-            const int32_t w = uw[u];
-            bool hit = false;
-            if (w <= last) {  // beyond the last label of row kappa nothing matches
-                int32_t q = -1;
-                if (MODE == kModeBitmap) {
-                    const int32_t off = w - k - 1;
-                    const uint2 bw = s_bm[off >> 5];
-                    const uint32_t bit = (uint32_t)off & 31u;
-                    if ((bw.x >> bit) & 1u) q = (int32_t)(bw.y + __popc(bw.x & ((1u << bit) - 1u)));
-                } else if (MODE == kModeKeys) {
-                    const int32_t qq = lower_bound_i32(s_keys, d, w);
-                    if (s_keys[qq] == w) q = qq;
-                } else {
-                    const int32_t qq = lower_bound_i32(col + rs, d, w);
-                    if (col[rs + qq] == w) q = qq;
-                }
-                if (q >= 0) {
-                    hit = true;
-                    if (MODE != kModeGlobal) atomicAdd(&s_acc[q], 1);
-                    else atomicAdd(&x.S[rs + q], 1);
-                }
+            for (int u = 0; u < kHubUnroll; ++u) {
+                const int32_t off = uw[u] <= last ? uw[u] - k - 1 : 0;
+                bw[u] = reinterpret_cast<const unsigned long long*>(s_bm)[off >> 5];
             }
-            hb[u] = __ballot(hit);
+#pragma unroll
+            for (int u = 0; u < kHubUnroll; ++u) {
+                const int32_t off = uw[u] - k - 1;
+                const uint32_t bits = (uint32_t)bw[u], bit = (uint32_t)off & 31u;
+                const bool hit = uw[u] <= last && ((bits >> bit) & 1u);
+                if (hit) atomicAdd(&s_acc[(uint32_t)(bw[u] >> 32) + __popc(bits & ((1u << bit) - 1u))], 1);
+                hb[u] = __ballot(hit);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < kHubUnroll; ++u) {
+                const int32_t w = uw[u];
+                bool hit = false;
+                if (w <= last) {  // beyond the last label of row kappa nothing matches
+                    int32_t q = -1;
+                    if (MODE == kModeKeys) {
+                        const int32_t qq = lower_bound_i32(s_keys, d, w);
+                        if (s_keys[qq] == w) q = qq;
+                    } else {
+                        const int32_t qq = lower_bound_i32(col + rs, d, w);
+                        if (col[rs + qq] == w) q = qq;
+                    }
+                    if (q >= 0) {
+                        hit = true;
+                        if (MODE != kModeGlobal) atomicAdd(&s_acc[q], 1);
+                        else atomicAdd(&x.S[rs + q], 1);
+                    }
+                }
+                hb[u] = __ballot(hit);
+            }
         }
         // S(i, w) of chunks past kHitWords (tails longer than 64 * kHitWords),
         // after the lookups so that no memory operation sits among them
@@ -244,8 +270,6 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
                                                            unsigned long long* __restrict__ cycles) {
     __shared__ uint2 s_bm[kSpanWords];   // rank bitmap {bits, set bits before this word}; or keys
     __shared__ int32_t s_acc[kKeyCap];
-    __shared__ int32_t s_e[kHubChunk];
-    __shared__ int32_t s_tl[kHubChunk];
     __shared__ int s_wave[kHubThreads / 64];
     __shared__ int32_t s_it;
     if (ctl->done) return;
@@ -267,10 +291,6 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
         const int32_t k = h.k, c0 = h.c0, rs = h.rs, d = h.d, last = h.last;
         const unsigned long long t_start = cycles ? (unsigned long long)clock64() : 0ull;
         const int32_t ntask = h.c1 - c0;
-        if (t < ntask) {
-            s_e[t] = c.edge[c0 + t];
-            s_tl[t] = ctail[c0 + t];
-        }
         const int32_t span = last - k;  // labels of row kappa lie in (k, last]
         const int mode = d > kKeyCap ? kModeGlobal : (span <= kSpanCap ? kModeBitmap : kModeKeys);
         int32_t* s_keys = reinterpret_cast<int32_t*>(s_bm);
@@ -301,11 +321,11 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
         __syncthreads();
 
         if (mode == kModeBitmap)
-            hub_tasks<kModeBitmap>(x, hitw, s_e, s_tl, ntask, k, rs, d, last, s_bm, s_acc);
+            hub_tasks<kModeBitmap>(x, hitw, c.edge, ctail, c0, ntask, k, rs, d, last, s_bm, s_acc);
         else if (mode == kModeKeys)
-            hub_tasks<kModeKeys>(x, hitw, s_e, s_tl, ntask, k, rs, d, last, s_bm, s_acc);
+            hub_tasks<kModeKeys>(x, hitw, c.edge, ctail, c0, ntask, k, rs, d, last, s_bm, s_acc);
         else
-            hub_tasks<kModeGlobal>(x, hitw, s_e, s_tl, ntask, k, rs, d, last, s_bm, s_acc);
+            hub_tasks<kModeGlobal>(x, hitw, c.edge, ctail, c0, ntask, k, rs, d, last, s_bm, s_acc);
         __syncthreads();
         if (mode != kModeGlobal)
             for (int32_t q = t; q < d; q += kHubThreads) {
