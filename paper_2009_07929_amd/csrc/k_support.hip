@@ -120,12 +120,16 @@ __device__ __forceinline__ void wave_task(const Buf& x, int32_t e) {
 enum { kModeBitmap = 0, kModeKeys = 1, kModeGlobal = 2 };
 static_assert(kHubChunk <= kHubThreads, "each wave holds at most 64 of an item's tasks in registers");
 
-// The task loop of one hub item, for one wave.  The wave walks the 64-element
-// chunks of its tasks (kk = wave, wave + 4, ...) in order, kHubUnroll chunks
-// per step.  A step issues the tail loads of all its chunks, then does their
-// lookups (LDS), then writes their hit words and finished task counts with one
-// store and one atomic instruction (lane u carries chunk u): stores never sit
-// between a load and its use, so the wave waits for memory once per step.
+// The task loop of one hub item, for one wave.  The wave's tasks (kk = wave,
+// wave + 4, ...; at most 64, lane r holds task r) are cut into 64-element
+// chunks of their tails, numbered in task order.  For each block of 64
+// chunks every lane first finds its chunk's task (a binary search over the
+// lanes' chunk prefix sums) and keeps the chunk's descriptor in registers;
+// the wave then processes the block kHubUnroll chunks per step, reading the
+// descriptors with readlane: the loads of a step are issued together and no
+// per-chunk bookkeeping runs on the scalar unit.  Each chunk's hits are
+// collected in its lane (hit word, count) and written once per block with one
+// store and one atomic instruction.
 template <int MODE>
 __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __restrict__ hitw,
                                           const int32_t* __restrict__ cedge, const int32_t* __restrict__ ctail,
@@ -134,133 +138,116 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
     const int32_t* __restrict__ col = x.col;
     const int32_t* s_keys = reinterpret_cast<const int32_t*>(s_bm);
     const int lane = (int)(threadIdx.x & 63);
-    const int32_t wv = (int32_t)(threadIdx.x >> 6);
+    const int32_t wv = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));  // wave-uniform
     constexpr int kWaves = kHubThreads / 64;
-    // this wave's tasks wv, wv + 4, ... (at most 64): lane r holds task r's
-    // edge and tail length; the walk reads them with readlane
     const int32_t mine = wv + kWaves * lane;
     int32_t t_e = 0, t_L = 0;
     if (mine < ntask) {
         t_e = cedge[c0 + mine];
         t_L = ctail[c0 + mine];
     }
-    const int32_t nmine = ntask > wv ? (ntask - wv + kWaves - 1) / kWaves : 0;
-    int32_t r = 0, ch = 0, e_cur = 0, L_cur = 0;
-    auto next_task = [&]() {  // skip tasks with an empty tail
-        while (r < nmine) {
-            const int32_t L = __builtin_amdgcn_readlane(t_L, r);
-            if (L > 0) {
-                L_cur = L;
-                e_cur = __builtin_amdgcn_readlane(t_e, r);
-                return;
-            }
-            ++r;
-        }
-    };
-    next_task();
-    int32_t acc = 0;  // hits of the current task so far: S(i, kappa)
-    while (r < nmine) {
-        int32_t ue[kHubUnroll], uc[kHubUnroll], uL[kHubUnroll];
-        bool uv[kHubUnroll], ulast[kHubUnroll];
+    const int32_t t_nc = (t_L + 63) >> 6;          // chunks of task r
+    const int32_t t_P = wave_incl_scan(t_nc);       // chunks of tasks 0..r
+    const int32_t C = __builtin_amdgcn_readlane(t_P, 63);
+    for (int32_t b0 = 0; b0 < C; b0 += 64) {
+        // descriptor of chunk j = b0 + lane: its task r (smallest r with
+        // t_P[r] > j), the chunk index within the task, start and length
+        const int32_t j = b0 + lane;
+        int32_t lo = 0, hi = 63;
 #pragma unroll
-        for (int u = 0; u < kHubUnroll; ++u) {
-            uv[u] = r < nmine;
-            ue[u] = e_cur;
-            uc[u] = ch;
-            uL[u] = L_cur;
-            ulast[u] = (ch + 1) * 64 >= L_cur;
-            if (uv[u]) {
-                if (ulast[u]) {
-                    ch = 0;
-                    ++r;
-                    next_task();
-                } else {
-                    ++ch;
+        for (int st = 0; st < 6; ++st) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (__shfl(t_P, mid) > j) hi = mid;
+            else lo = mid + 1;
+        }
+        const bool dv = j < C;
+        const int32_t de = __shfl(t_e, lo), dL = __shfl(t_L, lo), dS = __shfl(t_P - t_nc, lo);
+        const int32_t dc = dv ? j - dS : 0;                   // chunk index within the task
+        const int32_t dbase = dv ? de + 1 + 64 * dc : 0;      // first tail position of the chunk
+        const int32_t dlen = dv ? min(64, dL - 64 * dc) : 0;  // elements in the chunk
+        const unsigned long long far = __ballot(dv && dc >= kHitWords);  // chunks whose hits add directly
+        const int32_t nch = min(64, C - b0);
+        uint32_t word_lo = 0, word_hi = 0;
+        int32_t cnt = 0;
+        for (int32_t jj = 0; jj < nch; jj += kHubUnroll) {
+            int32_t ub[kHubUnroll], ul[kHubUnroll], uw[kHubUnroll];
+#pragma unroll
+            for (int u = 0; u < kHubUnroll; ++u) {
+                const int32_t q = min(jj + u, 63);
+                ub[u] = __builtin_amdgcn_readlane(dbase, q);
+                ul[u] = jj + u < nch ? __builtin_amdgcn_readlane(dlen, q) : 0;
+            }
+            // unconditional loads (lanes past the chunk read its first element)
+#pragma unroll
+            for (int u = 0; u < kHubUnroll; ++u) {
+                const int32_t* base = col + ub[u];
+                uw[u] = base[lane < ul[u] ? lane : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < kHubUnroll; ++u)
+                if (lane >= ul[u]) uw[u] = INT32_MAX;
+            unsigned long long hb[kHubUnroll];
+            if (MODE == kModeBitmap) {
+                // all chunks' bitmap words first (independent LDS reads), then
+                // ranks and LDS accumulations
+                unsigned long long bw[kHubUnroll];
+#pragma unroll
+                for (int u = 0; u < kHubUnroll; ++u) {
+                    const int32_t off = uw[u] <= last ? uw[u] - k - 1 : 0;
+                    bw[u] = reinterpret_cast<const unsigned long long*>(s_bm)[off >> 5];
                 }
-            }
-        }
-        // unconditional loads (lanes past the tail read the task's own edge),
-        // so that the compiler can wait for them one at a time
-        int32_t uw[kHubUnroll];
-        bool uin[kHubUnroll];
 #pragma unroll
-        for (int u = 0; u < kHubUnroll; ++u) {
-            const int32_t o = uc[u] * 64 + lane;
-            uin[u] = uv[u] && o < uL[u];
-            uw[u] = col[uin[u] ? ue[u] + 1 + o : ue[u]];
-        }
+                for (int u = 0; u < kHubUnroll; ++u) {
+                    const int32_t off = uw[u] - k - 1;
+                    const uint32_t bits = (uint32_t)bw[u], bit = (uint32_t)off & 31u;
+                    const bool hit = uw[u] <= last && ((bits >> bit) & 1u);
+                    if (hit) atomicAdd(&s_acc[(uint32_t)(bw[u] >> 32) + __popc(bits & ((1u << bit) - 1u))], 1);
+                    hb[u] = __ballot(hit);
+                }
+            } else {
 #pragma unroll
-        for (int u = 0; u < kHubUnroll; ++u)
-            if (!uin[u]) uw[u] = INT32_MAX;
-        unsigned long long hb[kHubUnroll];
-        if (MODE == kModeBitmap) {
-            // all chunks' bitmap words first (independent LDS reads), then
-            // ranks and LDS accumulations
-            unsigned long long bw[kHubUnroll];
-#pragma unroll
-            for (int u = 0; u < kHubUnroll; ++u) {
-                const int32_t off = uw[u] <= last ? uw[u] - k - 1 : 0;
-                bw[u] = reinterpret_cast<const unsigned long long*>(s_bm)[off >> 5];
-            }
-#pragma unroll
-            for (int u = 0; u < kHubUnroll; ++u) {
-                const int32_t off = uw[u] - k - 1;
-                const uint32_t bits = (uint32_t)bw[u], bit = (uint32_t)off & 31u;
-                const bool hit = uw[u] <= last && ((bits >> bit) & 1u);
-                if (hit) atomicAdd(&s_acc[(uint32_t)(bw[u] >> 32) + __popc(bits & ((1u << bit) - 1u))], 1);
-                hb[u] = __ballot(hit);
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < kHubUnroll; ++u) {
-                const int32_t w = uw[u];
-                bool hit = false;
-                if (w <= last) {  // beyond the last label of row kappa nothing matches
-                    int32_t q = -1;
-                    if (MODE == kModeKeys) {
-                        const int32_t qq = lower_bound_i32(s_keys, d, w);
-                        if (s_keys[qq] == w) q = qq;
-                    } else {
-                        const int32_t qq = lower_bound_i32(col + rs, d, w);
-                        if (col[rs + qq] == w) q = qq;
+                for (int u = 0; u < kHubUnroll; ++u) {
+                    const int32_t w = uw[u];
+                    bool hit = false;
+                    if (w <= last) {  // beyond the last label of row kappa nothing matches
+                        int32_t q = -1;
+                        if (MODE == kModeKeys) {
+                            const int32_t qq = lower_bound_i32(s_keys, d, w);
+                            if (s_keys[qq] == w) q = qq;
+                        } else {
+                            const int32_t qq = lower_bound_i32(col + rs, d, w);
+                            if (col[rs + qq] == w) q = qq;
+                        }
+                        if (q >= 0) {
+                            hit = true;
+                            if (MODE != kModeGlobal) atomicAdd(&s_acc[q], 1);
+                            else atomicAdd(&x.S[rs + q], 1);
+                        }
                     }
-                    if (q >= 0) {
-                        hit = true;
-                        if (MODE != kModeGlobal) atomicAdd(&s_acc[q], 1);
-                        else atomicAdd(&x.S[rs + q], 1);
-                    }
+                    hb[u] = __ballot(hit);
                 }
-                hb[u] = __ballot(hit);
+            }
+            // the chunk's hit word and count go to its lane
+#pragma unroll
+            for (int u = 0; u < kHubUnroll; ++u) {
+                const int32_t q = jj + u;
+                if (q < nch && lane == q) {
+                    word_lo = (uint32_t)hb[u];
+                    word_hi = (uint32_t)(hb[u] >> 32);
+                    cnt = __popcll(hb[u]);
+                }
+            }
+            // S(i, w) of chunks past kHitWords (tails longer than 64 * kHitWords)
+            if (far) {
+#pragma unroll
+                for (int u = 0; u < kHubUnroll; ++u)
+                    if (jj + u < nch && ((far >> (jj + u)) & 1ull) && ((hb[u] >> lane) & 1ull))
+                        atomicAdd(&x.S[ub[u] + lane], 1);
             }
         }
-        // S(i, w) of chunks past kHitWords (tails longer than 64 * kHitWords),
-        // after the lookups so that no memory operation sits among them
-#pragma unroll
-        for (int u = 0; u < kHubUnroll; ++u)
-            if (uv[u] && uc[u] >= kHitWords && ((hb[u] >> lane) & 1ull))
-                atomicAdd(&x.S[ue[u] + 1 + uc[u] * 64 + lane], 1);
-        // lane u: hit word of chunk u, and the count of the task that chunk u ends
-        unsigned long long my_word = 0;
-        int64_t my_word_at = -1;
-        int32_t my_cnt = 0, my_cnt_at = -1;
-#pragma unroll
-        for (int u = 0; u < kHubUnroll; ++u) {
-            if (!uv[u]) continue;
-            acc += __popcll(hb[u]);
-            if (lane == u && uc[u] < kHitWords) {
-                my_word = hb[u];
-                my_word_at = (int64_t)ue[u] * kHitWords + uc[u];
-            }
-            if (ulast[u]) {
-                if (lane == u && acc) {
-                    my_cnt = acc;
-                    my_cnt_at = ue[u];
-                }
-                acc = 0;
-            }
-        }
-        if (my_word_at >= 0) hitw[my_word_at] = my_word;
-        if (my_cnt_at >= 0) atomicAdd(&x.S[my_cnt_at], my_cnt);
+        // block end: lane j writes chunk j's hit word and adds its count to S(i, kappa)
+        if (dv && dc < kHitWords) hitw[(int64_t)de * kHitWords + dc] = ((unsigned long long)word_hi << 32) | word_lo;
+        if (dv && cnt) atomicAdd(&x.S[de], cnt);
     }
 }
 
@@ -282,15 +269,18 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
     if (t == 0) s_it = atomicAdd(&ctl->item_next, 1);
     __syncthreads();
     for (;;) {
-        const int32_t it = n_items - 1 - s_it;
+        // item fields are workgroup-uniform: keep them in scalar registers
+        const int32_t it = __builtin_amdgcn_readfirstlane(n_items - 1 - s_it);
         if (it < 0) break;
         int32_t ticket = 0;
         if (t == 0) ticket = atomicAdd(&ctl->item_next, 1);
         const int32_t* __restrict__ col = x.col;
         const HubItem h = items[it];
-        const int32_t k = h.k, c0 = h.c0, rs = h.rs, d = h.d, last = h.last;
+        const int32_t k = __builtin_amdgcn_readfirstlane(h.k), c0 = __builtin_amdgcn_readfirstlane(h.c0),
+                      rs = __builtin_amdgcn_readfirstlane(h.rs), d = __builtin_amdgcn_readfirstlane(h.d),
+                      last = __builtin_amdgcn_readfirstlane(h.last);
         const unsigned long long t_start = cycles ? (unsigned long long)clock64() : 0ull;
-        const int32_t ntask = h.c1 - c0;
+        const int32_t ntask = __builtin_amdgcn_readfirstlane(h.c1) - c0;
         const int32_t span = last - k;  // labels of row kappa lie in (k, last]
         const int mode = d > kKeyCap ? kModeGlobal : (span <= kSpanCap ? kModeBitmap : kModeKeys);
         int32_t* s_keys = reinterpret_cast<int32_t*>(s_bm);
