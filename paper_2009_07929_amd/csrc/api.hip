@@ -144,6 +144,7 @@ Work carve(void* work, int32_t n, int64_t m, int32_t G) {
     w.sc.is_hub = (uint8_t*)(base + L.is_hub);
     w.sc.hub_row = (uint8_t*)(base + L.hub_row);
     w.sc.hitw = (unsigned long long*)(base + L.hitw);
+    w.sc.hit_stride = m;
     w.sc.wave_tasks = (int32_t*)(base + L.wave_tasks);
     w.sc.thread_tasks = (int32_t*)(base + L.thread_tasks);
     w.ctl = (Ctl*)(base + L.ctl);
@@ -321,7 +322,7 @@ int32_t support_pass(int sched, int32_t n, const Work& w, int p, const PassDims&
             return launch_support_hub(x, w.c[p], w.sc, dm.items, w.ctl, cycles, s);
         });
         if (rc == KTRUSS_OK && dm.items > 0)
-            rc = timed_launch(4, dm.m, s, [&] { return launch_hit_sum(x, w.sc, n, w.ctl, s); });
+            rc = timed_launch(4, dm.m, s, [&] { return launch_hit_sum(x, w.sc, &w.ctl->m_buf[p], dm.m, w.ctl, s); });
         if (rc == KTRUSS_OK && sched != KTRUSS_SCHED_FORCE_HUB) {
             rc = timed_launch(2, dm.n_wave, s, [&] {
                 return launch_support_wave(x, w.sc.wave_tasks, &w.ctl->n_wave, dm.n_wave, w.ctl, s);

@@ -100,7 +100,8 @@ struct Scratch {
     int32_t* rs_hist;     // int32[256 * ceil(m / kRsTile) + 1]: radix-sort digit histograms
     uint8_t* is_hub;      // uint8[n]
     uint8_t* hub_row;     // uint8[n]: row kappa has hub items in the current pass
-    unsigned long long* hitw;  // uint64[kHitWords * m]: hub hit words, task-major
+    unsigned long long* hitw;  // uint64[kHitWords * m]: hub hit words (hit_word_index)
+    int64_t hit_stride;        // edges of the workspace (m)
     int32_t* wave_tasks;  // int32[m]
     int32_t* thread_tasks;// int32[m]
 };
@@ -116,6 +117,13 @@ struct BatchCtx {
     uint8_t* mask;            // outputs, canonical positions of the union
     int32_t* support;
 };
+
+// Hit word c of the task of edge e: word 0 of all tasks edge-major (read
+// 64 tasks at a time by the row-local sum), words 1.. of a task together
+// (written together by the hub kernel).
+__host__ __device__ inline int64_t hit_word_index(int32_t e, int32_t c, int64_t stride) {
+    return c == 0 ? (int64_t)e : stride + (int64_t)e * (kHitWords - 1) + (c - 1);
+}
 
 struct Layout {
     size_t col[2], src[2], eid[2], S[2], rowptr[2];

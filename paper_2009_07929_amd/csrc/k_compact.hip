@@ -25,19 +25,22 @@ __device__ __forceinline__ bool round_keep(const Buf& x, const BatchCtx& b, int3
     return x.S[e] >= b.thrv[v];
 }
 
+// A policy reads what element i needs once (load), decides on it (keep) and
+// writes the survivor (emit) or handles the dropped element (drop).
 struct CsrRound {
     Buf x, y;
     int32_t thr;
     BatchCtx b;
+    __device__ int32_t load(int32_t e) const { return e; }
     __device__ bool keep(int32_t e) const { return round_keep(x, b, thr, e); }
-    __device__ void drop(int32_t e) const {
+    __device__ void drop(int32_t e, int32_t) const {
         if (b.thrv && b.done_now[b.gidv[x.src[e]]]) {
             const int32_t c = x.eid[e];
             b.mask[c] = 1;
             b.support[c] = x.S[e];
         }
     }
-    __device__ void emit(int32_t e, int32_t q) const {
+    __device__ void emit(int32_t e, int32_t, int32_t q) const {
         y.col[q] = x.col[e];
         y.src[q] = x.src[e];
         y.eid[q] = x.eid[e];
@@ -49,9 +52,10 @@ struct CsrRound {
 struct CsrAlive {
     Buf x, y;
     const uint8_t* alive_can;
+    __device__ int32_t load(int32_t e) const { return e; }
     __device__ bool keep(int32_t e) const { return alive_can[x.eid[e]] != 0; }
-    __device__ void drop(int32_t) const {}
-    __device__ void emit(int32_t e, int32_t q) const {
+    __device__ void drop(int32_t, int32_t) const {}
+    __device__ void emit(int32_t e, int32_t, int32_t q) const {
         y.col[q] = x.col[e];
         y.src[q] = x.src[e];
         y.eid[q] = x.eid[e];
@@ -60,23 +64,17 @@ struct CsrAlive {
 };
 
 // In-edge list entry c (an edge position of buffer x); it survives with its
-// edge and is rewritten to that edge's new position.
-template <int MODE>
+// edge and is rewritten to that edge's new position.  Runs after the CSR
+// filter, whose xscan holds q for a kept edge and ~q for a dropped one, so one
+// read decides and remaps.
 struct CscEntry {
-    Buf x;
     Csc cx, cy;
-    int32_t thr;
-    const uint8_t* alive_can;
-    const int32_t* xscan;  // new CSR positions
-    BatchCtx b;
-    __device__ bool keep(int32_t c) const {
-        const int32_t e = cx.edge[c];
-        if (MODE == 0) return round_keep(x, b, thr, e);
-        return alive_can[x.eid[e]] != 0;
-    }
-    __device__ void drop(int32_t) const {}
-    __device__ void emit(int32_t c, int32_t q) const {
-        cy.edge[q] = xscan[cx.edge[c]];
+    const int32_t* xscan;
+    __device__ int32_t load(int32_t c) const { return xscan[cx.edge[c]]; }
+    __device__ bool keep(int32_t v) const { return v >= 0; }
+    __device__ void drop(int32_t, int32_t) const {}
+    __device__ void emit(int32_t v, int32_t c, int32_t q) const {
+        cy.edge[q] = v;
         cy.src[q] = cx.src[c];
     }
 };
@@ -98,7 +96,7 @@ __global__ __launch_bounds__(kBlock) void k_filter_count(P pol, const Ctl* __res
     int32_t lo, hi;
     chunk_of(ctl->m_buf[p], lo, hi);
     int c = 0;
-    for (int32_t i = lo + (int32_t)threadIdx.x; i < hi; i += kBlock) c += pol.keep(i);
+    for (int32_t i = lo + (int32_t)threadIdx.x; i < hi; i += kBlock) c += pol.keep(pol.load(i));
     c = block_sum<kBlock>(c, s_wave);
     if (threadIdx.x == 0) blockcnt[blockIdx.x] = c;
 }
@@ -166,26 +164,28 @@ __global__ __launch_bounds__(kBlock) void k_filter_scatter(P pol, const Ctl* __r
     for (int32_t t0 = lo; t0 < hi; t0 += kBlock) {
         const int32_t i = t0 + (int32_t)threadIdx.x;
         const bool in = i < hi;
-        const bool k = in && pol.keep(i);
+        const int32_t v = in ? pol.load(i) : 0;
+        const bool k = in && pol.keep(v);
         int tot;
         const int32_t q = base + block_excl_flag<kBlock>(k, s_wave, tot);
         if (in) {
-            xscan[i] = q;
-            if (k) pol.emit(i, q);
-            else pol.drop(i);
+            xscan[i] = k ? q : ~q;  // new position; ~ marks a dropped element
+            if (k) pol.emit(v, i, q);
+            else pol.drop(v, i);
         }
         base += tot;
     }
 }
 
-// new_ptr[s] = xscan[old_ptr[s]] for s in [0, n]
+// new_ptr[s] = the new position of old_ptr[s] for s in [0, n]
 __global__ __launch_bounds__(kBlock) void k_ptr_remap(const int32_t* __restrict__ old_ptr, int32_t* __restrict__ new_ptr,
                                                     int32_t n, const int32_t* __restrict__ xscan,
                                                     const Ctl* __restrict__ ctl, int round) {
     if (round && ctl->done) return;
     const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (s > n) return;
-    new_ptr[s] = xscan[old_ptr[s]];
+    const int32_t v = xscan[old_ptr[s]];
+    new_ptr[s] = v < 0 ? ~v : v;
 }
 
 // Batched form: the run ends after the pass that leaves no edge.
@@ -226,13 +226,7 @@ hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* 
     }
     k_ptr_remap<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(x.rowptr, y.rowptr, n, sc.xscan, ctl, round);
     if (cx && cy) {
-        if (mode == 0) {
-            run_filter(CscEntry<0>{x, *cx, *cy, thr, nullptr, sc.xscan, b}, ctl, p, 0, 1, sc.blockcnt, sc.blockoff,
-                       sc.cxscan, m_hint, s);
-        } else {
-            run_filter(CscEntry<1>{x, *cx, *cy, 0, alive_can, sc.xscan, b}, ctl, p, 0, 0, sc.blockcnt, sc.blockoff,
-                       sc.cxscan, m_hint, s);
-        }
+        run_filter(CscEntry{*cx, *cy, sc.xscan}, ctl, p, 0, round, sc.blockcnt, sc.blockoff, sc.cxscan, m_hint, s);
         k_ptr_remap<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(cx->ptr, cy->ptr, n, sc.cxscan, ctl, round);
     }
     if (batch && mode == 0) k_batch_end<<<1, 64, 0, s>>>(ctl, p);

@@ -131,7 +131,7 @@ static_assert(kHubChunk <= kHubThreads, "each wave holds at most 64 of an item's
 // collected in its lane (hit word, count) and written once per block with one
 // store and one atomic instruction.
 template <int MODE>
-__device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __restrict__ hitw,
+__device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __restrict__ hitw, int64_t hit_stride,
                                           const int32_t* __restrict__ cedge, const int32_t* __restrict__ ctail,
                                           int32_t c0, int32_t ntask, int32_t k, int32_t rs, int32_t d, int32_t last,
                                           const uint2* s_bm, int32_t* s_acc) {
@@ -246,14 +246,15 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
             }
         }
         // block end: lane j writes chunk j's hit word and adds its count to S(i, kappa)
-        if (dv && dc < kHitWords) hitw[(int64_t)de * kHitWords + dc] = ((unsigned long long)word_hi << 32) | word_lo;
+        if (dv && dc < kHitWords)
+            hitw[hit_word_index(de, dc, hit_stride)] = ((unsigned long long)word_hi << 32) | word_lo;
         if (dv && cnt) atomicAdd(&x.S[de], cnt);
     }
 }
 
 __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const HubItem* __restrict__ items,
                                                            const int32_t* __restrict__ ctail, Ctl* ctl,
-                                                           unsigned long long* __restrict__ hitw,
+                                                           unsigned long long* __restrict__ hitw, int64_t hit_stride,
                                                            unsigned long long* __restrict__ cycles) {
     __shared__ uint2 s_bm[kSpanWords];   // rank bitmap {bits, set bits before this word}; or keys
     __shared__ int32_t s_acc[kKeyCap];
@@ -311,11 +312,11 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
         __syncthreads();
 
         if (mode == kModeBitmap)
-            hub_tasks<kModeBitmap>(x, hitw, c.edge, ctail, c0, ntask, k, rs, d, last, s_bm, s_acc);
+            hub_tasks<kModeBitmap>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, rs, d, last, s_bm, s_acc);
         else if (mode == kModeKeys)
-            hub_tasks<kModeKeys>(x, hitw, c.edge, ctail, c0, ntask, k, rs, d, last, s_bm, s_acc);
+            hub_tasks<kModeKeys>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, rs, d, last, s_bm, s_acc);
         else
-            hub_tasks<kModeGlobal>(x, hitw, c.edge, ctail, c0, ntask, k, rs, d, last, s_bm, s_acc);
+            hub_tasks<kModeGlobal>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, rs, d, last, s_bm, s_acc);
         __syncthreads();
         if (mode != kModeGlobal)
             for (int32_t q = t; q < d; q += kHubThreads) {
@@ -352,46 +353,55 @@ __device__ __forceinline__ unsigned long long transpose64(unsigned long long v, 
 // Row-local sum of the hub kernel's hit words: S(i, w) of the edge at
 // position p of row i gains one for every earlier task j of row i (a hub task:
 // hub_row[col[j]]) whose hit words have the bit of tail offset p - j - 1.
-// One wave per row, 64 positions at a time: each lane takes a task, aligns the
-// task's words to the 64 positions (a funnel shift of two words), and a bit
-// transpose plus popcount turns the 64 aligned words into 64 per-position
-// counts.  Only tasks within kHitWords words of the block have words.
+// One wave per window of 64 positions P0 .. P0+63.  Lane l takes the task at
+// P0 + l and shifts its first word so that bit l' stands for position P0 + l';
+// a 64x64 bit transpose and a popcount then give every position the hits of
+// the window's own tasks (a task has no hits past its row, so tasks of other
+// rows add nothing).  The only earlier tasks that reach into the window are
+// those of the row holding P0 when it starts before P0: their words are
+// aligned to the window with a funnel shift of two words and summed the same
+// way, 64 tasks at a time, from at most 64 * kHitWords positions back.
 __global__ __launch_bounds__(kBlock) void k_hit_sum(Buf x, const unsigned long long* __restrict__ hitw,
-                                                  const uint8_t* __restrict__ hub_row, int32_t n,
-                                                  const Ctl* __restrict__ ctl) {
+                                                  int64_t stride, const uint8_t* __restrict__ hub_row,
+                                                  const int32_t* __restrict__ count, const Ctl* __restrict__ ctl) {
     if (ctl->done) return;
+    const int32_t m = *count;
     const int lane = (int)(threadIdx.x & 63);
-    const int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    if (i >= n) return;
-    const int32_t rs = x.rowptr[i], d = x.rowptr[i + 1] - rs;
-    if (d < 2) return;
+    const int64_t P0l = ((int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * 64;
+    if (P0l >= m) return;  // whole wave
+    const int32_t P0 = (int32_t)P0l;
     const int32_t* __restrict__ col = x.col;
-    const int32_t nb = (d + 63) >> 6;
-    for (int32_t pb = 0; pb < nb; ++pb) {
-        const int32_t p0 = pb * 64;
-        uint32_t add = 0;
-        for (int32_t tb = max(0, pb - kHitWords); tb <= pb; ++tb) {
-            const int32_t j = tb * 64 + lane;  // this lane's task (row-local)
-            unsigned long long v = 0;
-            if (j < d - 1 && hub_row[col[rs + j]]) {
-                const unsigned long long* __restrict__ hw = hitw + (size_t)(rs + j) * kHitWords;
-                const int32_t L = d - 1 - j;   // tail length; words 0 .. ceil(L/64)-1 (below kHitWords) exist
-                const int32_t t0 = p0 - j - 1;  // tail offset of position p0
-                if (t0 < 0) {
-                    const int32_t sh = -t0;  // 1..64: position p0 + sh is tail offset 0
-                    v = sh < 64 ? (hw[0] << sh) : 0ull;
-                } else {
-                    const int32_t c = t0 >> 6, sft = t0 & 63;
-                    const unsigned long long lo = (c < kHitWords && c * 64 < L) ? hw[c] : 0ull;
-                    const unsigned long long hi = (c + 1 < kHitWords && (c + 1) * 64 < L) ? hw[c + 1] : 0ull;
-                    v = sft ? ((lo >> sft) | (hi << (64 - sft))) : lo;
-                }
-            }
-            add += (uint32_t)__popcll(transpose64(v, lane));
-        }
-        const int32_t p = p0 + lane;
-        if (p < d && add) x.S[rs + p] += (int32_t)add;
+    const int32_t p = P0 + lane;
+    const bool in = p < m;
+    int32_t row = 0;
+    unsigned long long v = 0;
+    if (in) {
+        row = x.src[p];
+        const int32_t sh = lane + 1;  // position P0 + sh is tail offset 0 of task p
+        // words exist for hub tasks with a non-empty tail
+        if (sh < 64 && p + 1 < x.rowptr[row + 1] && hub_row[col[p]]) v = hitw[p] << sh;
     }
+    uint32_t add = (uint32_t)__popcll(transpose64(v, lane));
+    const int32_t r0 = __shfl(row, 0);  // the row holding P0
+    const int32_t r0s = x.rowptr[r0], r0e = x.rowptr[r0 + 1];
+    if (r0s < P0) {
+        for (int32_t j0 = max(r0s, P0 - 64 * kHitWords); j0 < P0; j0 += 64) {
+            const int32_t j = j0 + lane;
+            unsigned long long w = 0;
+            if (j < P0 && hub_row[col[j]]) {
+                const int32_t L = r0e - j - 1;   // tail length of task j
+                const int32_t t0 = P0 - j - 1;   // tail offset of position P0 (>= 0)
+                const int32_t c = t0 >> 6, sft = t0 & 63;
+                const unsigned long long lo =
+                    (c < kHitWords && c * 64 < L) ? hitw[hit_word_index(j, c, stride)] : 0ull;
+                const unsigned long long hi =
+                    (c + 1 < kHitWords && (c + 1) * 64 < L) ? hitw[hit_word_index(j, c + 1, stride)] : 0ull;
+                w = sft ? ((lo >> sft) | (hi << (64 - sft))) : lo;
+            }
+            add += (uint32_t)__popcll(transpose64(w, lane));
+        }
+    }
+    if (in && add) x.S[p] += (int32_t)add;
 }
 
 }  // namespace
@@ -414,14 +424,16 @@ hipError_t launch_support_hub(const Buf& x, const Csc& c, const Scratch& sc, int
                               unsigned long long* cycles, hipStream_t s) {
     if (n_items_hint <= 0) return hipSuccess;
     k_support_hub<<<min(n_items_hint, kHubMaxGrid), kHubThreads, 0, s>>>(x, c, sc.items, sc.ctail, ctl, sc.hitw,
-                                                                        cycles);
+                                                                        sc.hit_stride, cycles);
     return hipGetLastError();
 }
 
-hipError_t launch_hit_sum(const Buf& x, const Scratch& sc, int32_t n, const Ctl* ctl, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)(((int64_t)n + kBlock / 64 - 1) / (kBlock / 64));  // one wave per row
-    k_hit_sum<<<grid, kBlock, 0, s>>>(x, sc.hitw, sc.hub_row, n, ctl);
+hipError_t launch_hit_sum(const Buf& x, const Scratch& sc, const int32_t* m_count, int32_t m_hint, const Ctl* ctl,
+                          hipStream_t s) {
+    if (m_hint <= 0) return hipSuccess;
+    const int64_t windows = ((int64_t)m_hint + 63) / 64;
+    const unsigned grid = (unsigned)((windows + kBlock / 64 - 1) / (kBlock / 64));  // one wave per window
+    k_hit_sum<<<grid, kBlock, 0, s>>>(x, sc.hitw, sc.hit_stride, sc.hub_row, m_count, ctl);
     return hipGetLastError();
 }
 
