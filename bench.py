@@ -11,6 +11,10 @@ Extra legs (on by default, --no-extras to skip), reported inside the same line:
   batched: 4096 Chung-Lu graphs (K per graph) in one batched run, edges/s =
            sum of edges / batch time, next to the same graphs run one at a time
            with the plain thread-per-edge kernel and with the main schedule.
+  learned: R-MAT scale 22 (0.6, 0.2, 0.15, 0.05) and Barabasi-Albert n=4M,
+           m=8, K = 3, 6, 10: the learned schedule (trained cost model) next to
+           the static degree heuristic, the all-hub schedule and the plain
+           kernel, edges/s per K, results checked identical.
 
 Prints one JSON line.  Only one GPU is used; --gpus above 1 exits.
 """
@@ -238,6 +242,55 @@ def batched_leg(args, kt, torch, count):
     return out
 
 
+def learned_leg(args, kt, torch, workloads=("rmat-s22-ef16", "ba-4M-m8")):
+    """The learned schedule (trained cost model) against the static degree
+    heuristic, the all-hub schedule and the plain thread-per-edge kernel on
+    the evaluation graphs: edges/s per K, results checked equal across
+    schedules."""
+    import numpy as np
+    import synth
+    from paper_2009_07929_amd import cost_model
+    params = cost_model.load_params("cuda:0")
+    if params is None:
+        return {"error": "no trained cost-model weights"}
+    out = {}
+    stream = torch.cuda.current_stream()
+    for wname in workloads:
+        w = synth.WORKLOADS[wname]
+        n, s, d = synth.workload_pairs(wname)
+        rowptr, col, _ = kt.ktruss_build_csr(s, d, n)
+        del s, d
+        m = len(col)
+        g = kt.Graph(rowptr, col, device="cuda:0")
+        mask = torch.empty(m, dtype=torch.uint8, device="cuda:0")
+        sup = torch.empty(m, dtype=torch.int32, device="cuda:0")
+        res = {"n": n, "m": m}
+        digest = {}
+        for sname in ("plain", "heuristic", "learned", "hub"):
+            kt.ktruss_set_schedule(g, SCHEDULES[sname], params if sname == "learned" else None, tuning(kt, 0))
+            per = {}
+            for K in w.Ks:
+                kt.ktruss_run(g, K, mask, sup, stream)  # warm-up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, _, r = kt.ktruss_run(g, K, mask, sup, stream)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                dg = (r, int(mask.sum().item()), int(sup.to(torch.int64).sum().item()))
+                if digest.setdefault(K, dg) != dg:
+                    raise RuntimeError("schedule %s disagrees on %s K=%d" % (sname, wname, K))
+                per[str(K)] = {"ms": dt * 1e3, "edges_per_s": m / dt, "rounds": r}
+            tot = sum(v["ms"] for v in per.values())
+            res[sname] = {"per_K": per, "edges_per_s": len(w.Ks) * m / (tot * 1e-3)}
+            log("learned leg: %s %s %.3e edges/s" % (wname, sname, res[sname]["edges_per_s"]))
+        res["learned_vs_heuristic"] = res["learned"]["edges_per_s"] / res["heuristic"]["edges_per_s"]
+        res["learned_vs_plain"] = res["learned"]["edges_per_s"] / res["plain"]["edges_per_s"]
+        res["learned_vs_hub"] = res["learned"]["edges_per_s"] / res["hub"]["edges_per_s"]
+        out[wname] = res
+        del g, mask, sup
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +334,8 @@ def main():
     if not args.no_extras:
         log("batched leg ...")
         out["batched"] = batched_leg(args, kt, torch, args.batch_graphs)
+        log("learned-schedule leg ...")
+        out["learned"] = learned_leg(args, kt, torch)
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
