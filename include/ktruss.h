@@ -222,9 +222,7 @@ int32_t ktruss_set_schedule(ktruss_graph* g, int32_t mode, const float* mlp_para
  * Kernel timing, a measurement aid.  While enabled (on != 0), the support
  * launches issued by ktruss_support / ktruss_run in this process are bracketed
  * by HIP events recorded on the call's stream and tallied by kind:
- *   0  the whole support pass (all variants of one pass), 16 compulsory bytes
- *      per alive edge (its column, its row, one read and one write of its
- *      support word) plus 4 per row pointer;
+ *   0  the whole support pass (all variants of one pass);
  *   1  thread-per-edge launches, 2 wavefront-per-edge launches, 3 hub-row
  *      launches (tasks = edge tasks, or hub items for kind 3);
  *   4  the row-local sum that adds the hub kernel's per-task hit words to
@@ -234,8 +232,13 @@ int32_t ktruss_set_schedule(ktruss_graph* g, int32_t mode, const float* mlp_para
 int32_t ktruss_profile_enable(int32_t on);
 /*
  * Reads the tallies of `kind` since the last enable: launches, summed time in
- * milliseconds (synchronises on the recorded events), tasks and compulsory
- * bytes.  Any out pointer may be NULL.  E_INVALID for a kind outside 0..4.
+ * milliseconds (synchronises on the recorded events) and tasks.  `bytes` is
+ * set for kind 0 only (0 otherwise): the algorithmic bytes of the profiled
+ * passes under the merge model of Algorithm 3, 4 (3 m + W) bytes read plus
+ * 8 (2 T + m) bytes of support read-modify-writes, with m the alive edges, W
+ * the sum over them of |tail of the edge in its row| + |row kappa| and T the
+ * triangles (the sum of the supports over 3), summed over the passes.
+ * Any out pointer may be NULL.  E_INVALID for a kind outside 0..4.
  */
 int32_t ktruss_profile_read(int32_t kind, int64_t* launches, double* total_ms, int64_t* tasks, int64_t* bytes);
 

@@ -225,6 +225,7 @@ struct Profile {
     std::vector<hipEvent_t> pool;
     int64_t launches[kKinds] = {}, tasks[kKinds] = {}, bytes[kKinds] = {};
     double ms[kKinds] = {};
+    unsigned long long* work_dev = nullptr;  // device {merge-model work, support sum} of the profiled passes
 };
 Profile& prof() {
     static Profile p;
@@ -284,10 +285,19 @@ template <class F>
 int32_t timed_launch(int kind, int64_t tasks, hipStream_t s, F&& launch) {
     if (tasks <= 0) return KTRUSS_OK;
     Timer t;
-    int32_t rc = timer_begin(t, kind, tasks, 16 * tasks, s);
+    int32_t rc = timer_begin(t, kind, tasks, 0, s);
     if (rc != KTRUSS_OK) return rc;
     HIP_TRY(launch(), "support launch");
     return timer_end(t, s);
+}
+
+// Device accumulator of the profiled passes' merge-model work, or null when
+// not profiling (or while capturing a graph).
+unsigned long long* profile_work() {
+    if (t_capturing) return nullptr;
+    Profile& P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    return P.on ? P.work_dev : nullptr;
 }
 
 bool uses_csc(int sched) { return sched != KTRUSS_SCHED_PLAIN && sched != KTRUSS_SCHED_FORCE_WAVE; }
@@ -307,7 +317,7 @@ int32_t support_pass(int sched, int32_t n, const Work& w, int p, const PassDims&
                      unsigned long long* cycles = nullptr) {
     const Buf& x = w.b[p];
     Timer tp;
-    int32_t rc = timer_begin(tp, 0, dm.m, 16 * (int64_t)dm.m + 4 * ((int64_t)n + 1), s);
+    int32_t rc = timer_begin(tp, 0, dm.m, 0, s);
     if (rc != KTRUSS_OK) return rc;
     if (sched == KTRUSS_SCHED_PLAIN) {
         rc = timed_launch(1, dm.m, s, [&] {
@@ -334,7 +344,11 @@ int32_t support_pass(int sched, int32_t n, const Work& w, int p, const PassDims&
         }
     }
     if (rc != KTRUSS_OK) return rc;
-    return timer_end(tp, s);
+    rc = timer_end(tp, s);
+    if (rc != KTRUSS_OK) return rc;
+    if (unsigned long long* acc = profile_work())
+        HIP_TRY(launch_pass_work(x, &w.ctl->m_buf[p], dm.m, w.ctl, acc, s), "pass work");
+    return KTRUSS_OK;
 }
 
 int32_t read_ctl(const Work& w, Ctl& h, hipStream_t s) {
@@ -544,6 +558,22 @@ int32_t ktruss_profile_enable(int32_t on) {
         P.launches[k] = P.tasks[k] = P.bytes[k] = 0;
         P.ms[k] = 0.0;
     }
+    if (P.on) {
+        if (!P.work_dev) {
+            hipError_t e = hipMalloc((void**)&P.work_dev, 2 * sizeof(unsigned long long));
+            if (e != hipSuccess) {
+                P.work_dev = nullptr;
+                P.on = false;
+                return fail_hip(e, "profile accumulator");
+            }
+        }
+        hipError_t e = hipMemset(P.work_dev, 0, 2 * sizeof(unsigned long long));
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) {
+            P.on = false;
+            return fail_hip(e, "profile accumulator");
+        }
+    }
     return KTRUSS_OK;
 }
 
@@ -565,7 +595,18 @@ int32_t ktruss_profile_read(int32_t kind, int64_t* launches, double* total_ms, i
     if (launches) *launches = P.launches[kind];
     if (total_ms) *total_ms = P.ms[kind];
     if (tasks) *tasks = P.tasks[kind];
-    if (bytes) *bytes = P.bytes[kind];
+    if (bytes) {
+        *bytes = 0;
+        if (kind == 0 && P.work_dev) {
+            // merge-model algorithmic bytes of the profiled passes:
+            // 4 (3 m + sum of tail and row-kappa lengths) reads + 8 (2 T + m) atomic read-writes
+            unsigned long long h[2] = {0, 0};
+            hipError_t e = hipMemcpy(h, P.work_dev, sizeof(h), hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return fail_hip(e, "profile accumulator read");
+            const int64_t m = P.tasks[0], T = (int64_t)(h[1] / 3);
+            *bytes = 4 * (3 * m + (int64_t)h[0]) + 8 * (2 * T + m);
+        }
+    }
     return KTRUSS_OK;
 }
 

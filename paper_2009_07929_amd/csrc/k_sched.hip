@@ -285,9 +285,8 @@ __global__ __launch_bounds__(kBlock) void k_in_outdeg_sum(Buf x, Csc c, int32_t 
     int32_t key = -1;
     long long v = 0;
     if (i < m) {
-        const int32_t e = c.edge[i];
-        const int32_t r = x.src[e];
-        key = x.col[e];
+        const int32_t r = c.src[i];
+        key = x.col[c.edge[i]];
         v = x.rowptr[r + 1] - x.rowptr[r];
     }
 #pragma unroll

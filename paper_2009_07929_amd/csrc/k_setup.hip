@@ -41,20 +41,34 @@ __global__ __launch_bounds__(kBlock) void k_validate_rowptr(const int32_t* __res
 // One thread per row: columns strictly ascending, above the diagonal, below n.
 // Also writes each edge's row into src_out.  Skipped when rowptr is invalid,
 // so a malformed rowptr is never walked.
+// Columns of every row strictly ascending, above the diagonal and below n;
+// also writes the row of every edge.  Each thread takes kValSpan consecutive
+// edges, finds the row of the first by binary search over rowptr (already
+// checked monotone) and walks on, so long rows cost no more than short ones.
+constexpr int kValSpan = 16;
+
 __global__ __launch_bounds__(kBlock) void k_validate_rows(const int32_t* __restrict__ rowptr,
-                                                        const int32_t* __restrict__ col, int32_t n,
+                                                        const int32_t* __restrict__ col, int32_t n, int32_t m,
                                                         int32_t* __restrict__ src_out, Ctl* ctl) {
     if (ctl->err) return;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const int32_t b = rowptr[i], e = rowptr[i + 1];
-    int32_t prev = (int32_t)i;
+    const int64_t p0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kValSpan;
+    if (p0 >= m) return;
+    // row = last i with rowptr[i] <= p0
+    int32_t lo = 0, hi = n;  // rowptr[lo] <= p0 < rowptr[hi]
+    while (hi - lo > 1) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (rowptr[mid] <= p0) lo = mid;
+        else hi = mid;
+    }
+    int32_t row = lo, next = rowptr[row + 1];
+    const int32_t p1 = (int32_t)min(p0 + kValSpan, (int64_t)m);
     int bad = 0;
-    for (int32_t p = b; p < e; ++p) {
+    for (int32_t p = (int32_t)p0; p < p1; ++p) {
+        while (p >= next) next = rowptr[++row + 1];
+        const int32_t prev = p == rowptr[row] ? row : col[p - 1];
         const int32_t c = col[p];
         bad |= (c <= prev) | (c >= n);
-        prev = c;
-        src_out[p] = (int32_t)i;
+        src_out[p] = row;
     }
     if (bad) atomicOr(&ctl->err, 16);
 }
@@ -110,7 +124,9 @@ hipError_t launch_validate(const int32_t* rowptr, const int32_t* col, int32_t n,
                            Ctl* ctl, hipStream_t s) {
     k_ctl_reset<<<1, 64, 0, s>>>(ctl, m);
     k_validate_rowptr<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(rowptr, n, m, ctl);
-    if (n > 0) k_validate_rows<<<grid_for(n), kBlock, 0, s>>>(rowptr, col, n, src_out, ctl);
+    if (n > 0 && m > 0)
+        k_validate_rows<<<grid_for(((int64_t)m + kValSpan - 1) / kValSpan), kBlock, 0, s>>>(rowptr, col, n, m, src_out,
+                                                                                           ctl);
     return hipGetLastError();
 }
 

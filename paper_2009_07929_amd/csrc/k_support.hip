@@ -404,7 +404,48 @@ __global__ __launch_bounds__(kBlock) void k_hit_sum(Buf x, const unsigned long l
     if (in && add) x.S[p] += (int32_t)add;
 }
 
+// Measurement aid (profiling only): the merge-model work of the pass, sum over
+// alive edges e = (i, kappa) of |tail of e in row i| + |row kappa|, and the sum
+// of the supports (three times the triangles), added to acc[0] and acc[1].
+__global__ __launch_bounds__(kBlock) void k_pass_work(Buf x, const int32_t* __restrict__ count,
+                                                    const Ctl* __restrict__ ctl, unsigned long long* __restrict__ acc) {
+    __shared__ unsigned long long s_w[kBlock / 64], s_s[kBlock / 64];
+    const int32_t m = *count;
+    unsigned long long w = 0, sup = 0;
+    for (int32_t e = (int32_t)(blockIdx.x * kBlock + threadIdx.x); e < m; e += (int32_t)(gridDim.x * kBlock)) {
+        const int32_t k = x.col[e];
+        w += (unsigned long long)(x.rowptr[x.src[e] + 1] - e - 1) + (unsigned long long)(x.rowptr[k + 1] - x.rowptr[k]);
+        sup += (unsigned long long)x.S[e];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        w += __shfl_xor(w, o);
+        sup += __shfl_xor(sup, o);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        s_w[threadIdx.x >> 6] = w;
+        s_s[threadIdx.x >> 6] = sup;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < kBlock / 64; ++i) {
+            w += s_w[i];
+            sup += s_s[i];
+        }
+        atomicAdd(&acc[0], w);
+        atomicAdd(&acc[1], sup);
+    }
+    (void)ctl;
+}
+
 }  // namespace
+
+hipError_t launch_pass_work(const Buf& x, const int32_t* m_count, int32_t m_hint, const Ctl* ctl,
+                            unsigned long long* acc, hipStream_t s) {
+    if (m_hint <= 0) return hipSuccess;
+    k_pass_work<<<min(grid_for(m_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, m_count, ctl, acc);
+    return hipGetLastError();
+}
 
 hipError_t launch_support_thread(const Buf& x, const int32_t* tasks, const int32_t* count_dev, int32_t n_hint,
                                  const Ctl* ctl, hipStream_t s) {

@@ -56,6 +56,10 @@ hipError_t launch_support_wave(const Buf& x, const int32_t* tasks, const int32_t
 // cycles: per-row shader-clock totals of the hub items (cost-model samples), or null
 hipError_t launch_support_hub(const Buf& x, const Csc& c, const Scratch& sc, int32_t n_items_hint, Ctl* ctl,
                               unsigned long long* cycles, hipStream_t s);
+// Profiling: merge-model work and support sum of the pass just computed, added
+// to acc[0] and acc[1].
+hipError_t launch_pass_work(const Buf& x, const int32_t* m_count, int32_t m_hint, const Ctl* ctl,
+                            unsigned long long* acc, hipStream_t s);
 // Row-local sum of the hub kernel's hit words into S (one wave per 64 edges;
 // m_count: alive edges on the device, m_hint: an upper bound for the grid).
 hipError_t launch_hit_sum(const Buf& x, const Scratch& sc, const int32_t* m_count, int32_t m_hint, const Ctl* ctl,
