@@ -8,9 +8,10 @@ resident in HBM.  value = edges processed per second = (number of K values x m)
 complete K-truss), summed over the sweep.
 
 Extra legs (on by default, --no-extras to skip), reported inside the same line:
-  batched: 4096 Chung-Lu graphs (K per graph) in one batched run, edges/s =
-           sum of edges / batch time, next to the same graphs run one at a time
-           with the plain thread-per-edge kernel and with the main schedule.
+  batched: 4096 Chung-Lu graphs (K per graph) in one batched run with the
+           autotuner's cached schedule and tiles, edges/s = sum of edges /
+           batch time, next to the same graphs run one at a time with the plain
+           thread-per-edge kernel and with the main schedule.
   learned: R-MAT scale 22 (0.6, 0.2, 0.15, 0.05) and Barabasi-Albert n=4M,
            m=8, K = 3, 6, 10: the learned schedule (trained cost model) next to
            the static degree heuristic, the all-hub schedule and the plain
@@ -216,6 +217,13 @@ def batched_leg(args, kt, torch, count):
     log("batch: %d graphs, %d edges (prep %.1fs)" % (count, msum, t_prep))
     b = kt.Batch(csr, device="cuda:0", schedule=SCHEDULES[args.schedule])
     b.c.tuning = tuning(kt, args.rounds_per_sync)
+    cfg = None
+    if not args.no_autotune:  # the autotuner's cached choice for this batch class, if any
+        from paper_2009_07929_amd import autotune
+        key = autotune.batch_class(b.G, b.m_total)
+        if key in autotune.load_cache():
+            cfg = autotune.tuned_config(key)
+            autotune.apply(b, cfg)
     K_d = torch.from_numpy(Kg).cuda()
     mask = torch.empty(b.m_total, dtype=torch.uint8, device="cuda:0")
     sup = torch.empty(b.m_total, dtype=torch.int32, device="cuda:0")
@@ -232,7 +240,8 @@ def batched_leg(args, kt, torch, count):
     batch_rounds = rounds.cpu().numpy()
     out = {"workload": "chunglu-batch-%d" % count, "graphs": count, "edges": msum,
            "batched_edges_per_s": msum / t_batch, "batched_ms": t_batch * 1e3,
-           "max_rounds": int(batch_rounds.max()), "schedule": args.schedule}
+           "max_rounds": int(batch_rounds.max()),
+           "schedule": cfg["schedule"] if cfg else args.schedule, "autotuned": cfg}
     del b, mask, sup
     # the same graphs one at a time (graph and output buffers resident before timing)
     for name in ("plain", args.schedule):
@@ -317,6 +326,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched leg: ignore the autotuner's cached configuration")
     ap.add_argument("--batch-graphs", type=int, default=4096)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed region, copy a device buffer of this size 3 times (a plain copy "

@@ -199,13 +199,18 @@ __global__ __launch_bounds__(kBlock) void k_csc_rows(const int32_t* __restrict__
 }
 
 // Tail length of the task of every in-edge list entry of the pass: the part
-// of row i after the edge (Algorithm 3's a12(j+1:)).
+// of row i after the edge (Algorithm 3's a12(j+1:)).  Also clears the first
+// hit word of every edge, so that tasks the hub kernel does not run read as
+// having no hits.
 __global__ __launch_bounds__(kBlock) void k_task_tails(Buf x, Csc c, const Ctl* __restrict__ ctl, int p,
-                                                     int32_t* __restrict__ ctail) {
+                                                     int32_t* __restrict__ ctail,
+                                                     unsigned long long* __restrict__ hitw) {
     if (ctl->done) return;
     const int32_t m = ctl->m_buf[p];
-    for (int32_t q = (int32_t)(blockIdx.x * kBlock + threadIdx.x); q < m; q += (int32_t)(gridDim.x * kBlock))
+    for (int32_t q = (int32_t)(blockIdx.x * kBlock + threadIdx.x); q < m; q += (int32_t)(gridDim.x * kBlock)) {
         ctail[q] = x.rowptr[c.src[q] + 1] - c.edge[q] - 1;
+        hitw[hit_word_index(q, 0, 0)] = 0ull;
+    }
 }
 
 // ---- hub items
@@ -571,7 +576,8 @@ hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched,
     device_scan(hc, n, ctl, sc, sc.itemoff, &ctl->n_items, s);
     k_hub_items<<<grid_for(n), kBlock, 0, s>>>(hc, x.col, n, sc.itemoff, sc.items, sc.hub_row, ctl);
     if (m_hint > 0)
-        k_task_tails<<<min(grid_for(m_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, c, ctl, p, sc.ctail);
+        k_task_tails<<<min(grid_for(m_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, c, ctl, p, sc.ctail,
+                                                                                        sc.hitw);
     if (is_hub) {
         const int32_t wave_min = t.wave_min_work > 0 ? t.wave_min_work : kDefaultWaveMin;
         TaskClass tc{x, c, is_hub, wave_min};

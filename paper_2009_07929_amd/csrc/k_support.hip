@@ -354,10 +354,10 @@ __device__ __forceinline__ unsigned long long transpose64(unsigned long long v, 
 // position p of row i gains one for every earlier task j of row i (a hub task:
 // hub_row[col[j]]) whose hit words have the bit of tail offset p - j - 1.
 // One wave per window of 64 positions P0 .. P0+63.  Lane l takes the task at
-// P0 + l and shifts its first word so that bit l' stands for position P0 + l';
-// a 64x64 bit transpose and a popcount then give every position the hits of
-// the window's own tasks (a task has no hits past its row, so tasks of other
-// rows add nothing).  The only earlier tasks that reach into the window are
+// P0 + l and shifts its first word (cleared for tasks the hub kernel did not
+// run) so that bit l' stands for position P0 + l'; a 64x64 bit transpose and a
+// popcount then give every position the hits of the window's own tasks (a task
+// has no hits past its row, so tasks of other rows add nothing).  The only earlier tasks that reach into the window are
 // those of the row holding P0 when it starts before P0: their words are
 // aligned to the window with a funnel shift of two words and summed the same
 // way, 64 tasks at a time, from at most 64 * kHitWords positions back.
@@ -373,16 +373,11 @@ __global__ __launch_bounds__(kBlock) void k_hit_sum(Buf x, const unsigned long l
     const int32_t* __restrict__ col = x.col;
     const int32_t p = P0 + lane;
     const bool in = p < m;
-    int32_t row = 0;
-    unsigned long long v = 0;
-    if (in) {
-        row = x.src[p];
-        const int32_t sh = lane + 1;  // position P0 + sh is tail offset 0 of task p
-        // words exist for hub tasks with a non-empty tail
-        if (sh < 64 && p + 1 < x.rowptr[row + 1] && hub_row[col[p]]) v = hitw[p] << sh;
-    }
+    // word 0 of every task: cleared by the pass preparation, written by the
+    // hub kernel for its tasks; position P0 + lane + 1 is tail offset 0 of task p
+    const unsigned long long v = (in && lane < 63) ? hitw[hit_word_index(p, 0, stride)] << (lane + 1) : 0ull;
     uint32_t add = (uint32_t)__popcll(transpose64(v, lane));
-    const int32_t r0 = __shfl(row, 0);  // the row holding P0
+    const int32_t r0 = x.src[P0];  // the row holding P0
     const int32_t r0s = x.rowptr[r0], r0e = x.rowptr[r0 + 1];
     if (r0s < P0) {
         for (int32_t j0 = max(r0s, P0 - 64 * kHitWords); j0 < P0; j0 += 64) {
