@@ -169,23 +169,31 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
         const int32_t nch = min(64, C - b0);
         uint32_t word_lo = 0, word_hi = 0;
         int32_t cnt = 0;
+        // Software pipeline: the tail loads of the next step are issued before
+        // the lookups of this one.  Loads are unconditional (lanes past a
+        // chunk, and chunks past the block, read a valid position) so that the
+        // compiler can wait for exactly the loads a step needs.
+        int32_t ub[kHubUnroll], ul[kHubUnroll], lw[kHubUnroll];
+        auto fetch = [&](int32_t j0, int32_t* fb, int32_t* fl, int32_t* fw) {
+#pragma unroll
+            for (int u = 0; u < kHubUnroll; ++u) {
+                const int32_t q = min(j0 + u, 63);
+                fb[u] = __builtin_amdgcn_readlane(dbase, q);
+                fl[u] = j0 + u < nch ? __builtin_amdgcn_readlane(dlen, q) : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < kHubUnroll; ++u) {
+                const int32_t* base = col + fb[u];
+                fw[u] = base[lane < fl[u] ? lane : 0];
+            }
+        };
+        fetch(0, ub, ul, lw);
         for (int32_t jj = 0; jj < nch; jj += kHubUnroll) {
-            int32_t ub[kHubUnroll], ul[kHubUnroll], uw[kHubUnroll];
+            int32_t nb[kHubUnroll], nl[kHubUnroll], nw[kHubUnroll];
+            fetch(jj + kHubUnroll, nb, nl, nw);
+            int32_t uw[kHubUnroll];
 #pragma unroll
-            for (int u = 0; u < kHubUnroll; ++u) {
-                const int32_t q = min(jj + u, 63);
-                ub[u] = __builtin_amdgcn_readlane(dbase, q);
-                ul[u] = jj + u < nch ? __builtin_amdgcn_readlane(dlen, q) : 0;
-            }
-            // unconditional loads (lanes past the chunk read its first element)
-#pragma unroll
-            for (int u = 0; u < kHubUnroll; ++u) {
-                const int32_t* base = col + ub[u];
-                uw[u] = base[lane < ul[u] ? lane : 0];
-            }
-#pragma unroll
-            for (int u = 0; u < kHubUnroll; ++u)
-                if (lane >= ul[u]) uw[u] = INT32_MAX;
+            for (int u = 0; u < kHubUnroll; ++u) uw[u] = lane < ul[u] ? lw[u] : INT32_MAX;
             unsigned long long hb[kHubUnroll];
             if (MODE == kModeBitmap) {
                 // all chunks' bitmap words first (independent LDS reads), then
@@ -244,6 +252,12 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
                     if (jj + u < nch && ((far >> (jj + u)) & 1ull) && ((hb[u] >> lane) & 1ull))
                         atomicAdd(&x.S[ub[u] + lane], 1);
             }
+#pragma unroll
+            for (int u = 0; u < kHubUnroll; ++u) {
+                ub[u] = nb[u];
+                ul[u] = nl[u];
+                lw[u] = nw[u];
+            }
         }
         // block end: lane j writes chunk j's hit word and adds its count to S(i, kappa)
         if (dv && dc < kHitWords)
@@ -263,74 +277,94 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
     if (ctl->done) return;
     const int32_t n_items = ctl->n_items;
     const int t = threadIdx.x;
-    // Persistent: workgroups pull items from a device counter.  Items are laid
-    // out by ascending kappa and the heaviest rows carry the largest labels, so
-    // they are taken from the end first (longest work first).  The ticket of
-    // the next item is requested while the current one is processed.
+    const int32_t* __restrict__ col = x.col;
+    int32_t* s_keys = reinterpret_cast<int32_t*>(s_bm);
+    // Row kappa currently staged in LDS (workgroup-uniform), or cur_k = -1.
+    int32_t cur_k = -1, cur_rs = 0, cur_d = 0, cur_last = 0, cur_mode = kModeBitmap;
+    auto flush = [&]() {  // S(kappa, :) accumulated in LDS -> global
+        if (cur_k >= 0 && cur_mode != kModeGlobal)
+            for (int32_t q = t; q < cur_d; q += kHubThreads) {
+                const int32_t a = s_acc[q];
+                if (a) atomicAdd(&x.S[cur_rs + q], a);
+            }
+    };
+    // Persistent: workgroups pull tickets from a device counter; a ticket is
+    // kHubBatch consecutive items, so the counter sees few atomics.  Items are
+    // laid out by ascending kappa and the heaviest rows carry the largest
+    // labels, so they are taken from the end first (longest work first).  The
+    // items of one row are consecutive: a workgroup that takes several keeps
+    // the row staged and its accumulators, and flushes them once.  The next
+    // ticket is requested while the current one is processed.
     if (t == 0) s_it = atomicAdd(&ctl->item_next, 1);
     __syncthreads();
     for (;;) {
-        // item fields are workgroup-uniform: keep them in scalar registers
-        const int32_t it = __builtin_amdgcn_readfirstlane(n_items - 1 - s_it);
-        if (it < 0) break;
+        const int32_t first = n_items - 1 - __builtin_amdgcn_readfirstlane(s_it) * kHubBatch;
+        if (first < 0) break;
         int32_t ticket = 0;
         if (t == 0) ticket = atomicAdd(&ctl->item_next, 1);
-        const int32_t* __restrict__ col = x.col;
-        const HubItem h = items[it];
-        const int32_t k = __builtin_amdgcn_readfirstlane(h.k), c0 = __builtin_amdgcn_readfirstlane(h.c0),
-                      rs = __builtin_amdgcn_readfirstlane(h.rs), d = __builtin_amdgcn_readfirstlane(h.d),
-                      last = __builtin_amdgcn_readfirstlane(h.last);
-        const unsigned long long t_start = cycles ? (unsigned long long)clock64() : 0ull;
-        const int32_t ntask = __builtin_amdgcn_readfirstlane(h.c1) - c0;
-        const int32_t span = last - k;  // labels of row kappa lie in (k, last]
-        const int mode = d > kKeyCap ? kModeGlobal : (span <= kSpanCap ? kModeBitmap : kModeKeys);
-        int32_t* s_keys = reinterpret_cast<int32_t*>(s_bm);
-        if (mode == kModeBitmap) {
-            const int32_t nw = (span + 31) >> 5;
-            for (int32_t j = t; j < nw; j += kHubThreads) s_bm[j] = make_uint2(0u, 0u);
-            __syncthreads();
-            for (int32_t q = t; q < d; q += kHubThreads) {
-                const int32_t off = col[rs + q] - k - 1;
-                atomicOr(&s_bm[off >> 5].x, 1u << (off & 31));
+        for (int32_t it = first; it > first - kHubBatch && it >= 0; --it) {
+            // item fields are workgroup-uniform: keep them in scalar registers
+            const HubItem h = items[it];
+            const int32_t k = __builtin_amdgcn_readfirstlane(h.k), c0 = __builtin_amdgcn_readfirstlane(h.c0);
+            const int32_t ntask = __builtin_amdgcn_readfirstlane(h.c1) - c0;
+            const unsigned long long t_start = cycles ? (unsigned long long)clock64() : 0ull;
+            if (k != cur_k) {
+                __syncthreads();  // every wave is done adding into the previous row's accumulators
+                flush();
+                cur_k = k;
+                cur_rs = __builtin_amdgcn_readfirstlane(h.rs);
+                cur_d = __builtin_amdgcn_readfirstlane(h.d);
+                cur_last = __builtin_amdgcn_readfirstlane(h.last);
+                const int32_t rs = cur_rs, d = cur_d;
+                const int32_t span = cur_last - k;  // labels of row kappa lie in (k, last]
+                cur_mode = d > kKeyCap ? kModeGlobal : (span <= kSpanCap ? kModeBitmap : kModeKeys);
+                __syncthreads();  // the flush and the previous row's tasks are done with LDS
+                if (cur_mode == kModeBitmap) {
+                    const int32_t nw = (span + 31) >> 5;
+                    for (int32_t j = t; j < nw; j += kHubThreads) s_bm[j] = make_uint2(0u, 0u);
+                    __syncthreads();
+                    for (int32_t q = t; q < d; q += kHubThreads) {
+                        const int32_t off = col[rs + q] - k - 1;
+                        atomicOr(&s_bm[off >> 5].x, 1u << (off & 31));
+                    }
+                    __syncthreads();
+                    const int32_t per = (nw + kHubThreads - 1) / kHubThreads;
+                    const int32_t j0 = t * per, j1 = min(j0 + per, nw);
+                    int local = 0;
+                    for (int32_t j = j0; j < j1; ++j) local += __popc(s_bm[j].x);
+                    int tot;
+                    int run = block_excl_sum<kHubThreads>(local, s_wave, tot);
+                    for (int32_t j = j0; j < j1; ++j) {
+                        s_bm[j].y = (uint32_t)run;
+                        run += __popc(s_bm[j].x);
+                    }
+                } else if (cur_mode == kModeKeys) {
+                    for (int32_t q = t; q < d; q += kHubThreads) s_keys[q] = col[rs + q];
+                }
+                if (cur_mode != kModeGlobal)
+                    for (int32_t q = t; q < d; q += kHubThreads) s_acc[q] = 0;
+                __syncthreads();
             }
-            __syncthreads();
-            const int32_t per = (nw + kHubThreads - 1) / kHubThreads;
-            const int32_t j0 = t * per, j1 = min(j0 + per, nw);
-            int local = 0;
-            for (int32_t j = j0; j < j1; ++j) local += __popc(s_bm[j].x);
-            int tot;
-            int run = block_excl_sum<kHubThreads>(local, s_wave, tot);
-            for (int32_t j = j0; j < j1; ++j) {
-                s_bm[j].y = (uint32_t)run;
-                run += __popc(s_bm[j].x);
+            if (cur_mode == kModeBitmap)
+                hub_tasks<kModeBitmap>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, cur_rs, cur_d, cur_last,
+                                       s_bm, s_acc);
+            else if (cur_mode == kModeKeys)
+                hub_tasks<kModeKeys>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, cur_rs, cur_d, cur_last,
+                                     s_bm, s_acc);
+            else
+                hub_tasks<kModeGlobal>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, cur_rs, cur_d, cur_last,
+                                       s_bm, s_acc);
+            if (cycles) {  // per-row cost samples for the cost model (shader clock)
+                __syncthreads();
+                if (t == 0) atomicAdd(&cycles[k], (unsigned long long)clock64() - t_start);
             }
-        } else if (mode == kModeKeys) {
-            for (int32_t q = t; q < d; q += kHubThreads) s_keys[q] = col[rs + q];
         }
-        if (mode != kModeGlobal)
-            for (int32_t q = t; q < d; q += kHubThreads) s_acc[q] = 0;
-        __syncthreads();
-
-        if (mode == kModeBitmap)
-            hub_tasks<kModeBitmap>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, rs, d, last, s_bm, s_acc);
-        else if (mode == kModeKeys)
-            hub_tasks<kModeKeys>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, rs, d, last, s_bm, s_acc);
-        else
-            hub_tasks<kModeGlobal>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, rs, d, last, s_bm, s_acc);
-        __syncthreads();
-        if (mode != kModeGlobal)
-            for (int32_t q = t; q < d; q += kHubThreads) {
-                const int32_t a = s_acc[q];
-                if (a) atomicAdd(&x.S[rs + q], a);
-            }
-        if (cycles) {  // per-row cost samples for the cost model (shader clock)
-            __syncthreads();
-            if (t == 0) atomicAdd(&cycles[k], (unsigned long long)clock64() - t_start);
-        }
-        __syncthreads();  // every thread has read s_it and the item's LDS
+        __syncthreads();  // every thread has read s_it
         if (t == 0) s_it = ticket;
         __syncthreads();
     }
+    __syncthreads();  // the last row's tasks are done with LDS
+    flush();
 }
 
 // 64x64 bit transpose across a wave: lane j holds row j (bit l = entry
