@@ -57,7 +57,7 @@ FullLayout full_layout(int32_t n, int64_t m, int32_t G) {
     const size_t em1 = sizeof(int32_t) * ((size_t)m + 1);
     const size_t vn = sizeof(int32_t) * ((size_t)n + 1);
     for (int b = 0; b < 2; ++b) {
-        L.col[b] = take(em);
+        L.col[b] = take(em + sizeof(int32_t) * 64);  // 64 columns of slack: the hub kernel's chunk loads
         L.src[b] = take(em);
         L.eid[b] = take(em);
         L.S[b] = take(em);

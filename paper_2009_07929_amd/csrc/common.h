@@ -16,7 +16,7 @@ constexpr int kScanThreads = 1024;
 // workgroup-per-hub-row kernel
 constexpr int kHubThreads = 256;     // 4 waves
 constexpr int kHubChunk = 256;       // tasks (in-edges of one row kappa) per hub item
-constexpr int kHubUnroll = 6;        // tail chunks whose loads a hub wave issues together
+constexpr int kHubUnroll = 8;        // tail chunks whose loads a hub wave issues together
 constexpr int kHubBatch = 4;         // consecutive hub items per ticket of the persistent hub kernel
 constexpr int kSpanCap = 32768;      // widest label span staged as a rank bitmap
 constexpr int kSpanWords = kSpanCap / 32;

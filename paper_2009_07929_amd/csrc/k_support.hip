@@ -127,16 +127,18 @@ static_assert(kHubChunk <= kHubThreads, "each wave holds at most 64 of an item's
 // lanes' chunk prefix sums) and keeps the chunk's descriptor in registers;
 // the wave then processes the block kHubUnroll chunks per step, reading the
 // descriptors with readlane: the loads of a step are issued together and no
-// per-chunk bookkeeping runs on the scalar unit.  Each chunk's hits are
-// collected in its lane (hit word, count) and written once per block with one
-// store and one atomic instruction.
+// per-chunk bookkeeping runs on the scalar unit.  Each chunk's hit word goes
+// to its lane and is written once per block, with one store and one atomic
+// instruction.  In the bitmap case a label beyond row kappa is
+// clamped onto a zero guard word, so a lookup needs no compare-and-select.
 template <int MODE>
 __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __restrict__ hitw, int64_t hit_stride,
                                           const int32_t* __restrict__ cedge, const int32_t* __restrict__ ctail,
                                           int32_t c0, int32_t ntask, int32_t k, int32_t rs, int32_t d, int32_t last,
-                                          const uint2* s_bm, int32_t* s_acc) {
+                                          uint32_t guard, const uint2* s_bm, int32_t* s_acc) {
     const int32_t* __restrict__ col = x.col;
     const int32_t* s_keys = reinterpret_cast<const int32_t*>(s_bm);
+    const unsigned long long* s_bm64 = reinterpret_cast<const unsigned long long*>(s_bm);
     const int lane = (int)(threadIdx.x & 63);
     const int32_t wv = __builtin_amdgcn_readfirstlane((int32_t)(threadIdx.x >> 6));  // wave-uniform
     constexpr int kWaves = kHubThreads / 64;
@@ -168,56 +170,47 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
         const unsigned long long far = __ballot(dv && dc >= kHitWords);  // chunks whose hits add directly
         const int32_t nch = min(64, C - b0);
         uint32_t word_lo = 0, word_hi = 0;
-        int32_t cnt = 0;
-        // Software pipeline: the tail loads of the next step are issued before
-        // the lookups of this one.  Loads are unconditional (lanes past a
-        // chunk, and chunks past the block, read a valid position) so that the
-        // compiler can wait for exactly the loads a step needs.
-        int32_t ub[kHubUnroll], ul[kHubUnroll], lw[kHubUnroll];
-        auto fetch = [&](int32_t j0, int32_t* fb, int32_t* fl, int32_t* fw) {
-#pragma unroll
-            for (int u = 0; u < kHubUnroll; ++u) {
-                const int32_t q = min(j0 + u, 63);
-                fb[u] = __builtin_amdgcn_readlane(dbase, q);
-                fl[u] = j0 + u < nch ? __builtin_amdgcn_readlane(dlen, q) : 0;
-            }
-#pragma unroll
-            for (int u = 0; u < kHubUnroll; ++u) {
-                const int32_t* base = col + fb[u];
-                fw[u] = base[lane < fl[u] ? lane : 0];
-            }
-        };
-        fetch(0, ub, ul, lw);
         for (int32_t jj = 0; jj < nch; jj += kHubUnroll) {
-            int32_t nb[kHubUnroll], nl[kHubUnroll], nw[kHubUnroll];
-            fetch(jj + kHubUnroll, nb, nl, nw);
-            int32_t uw[kHubUnroll];
+            int32_t ub[kHubUnroll], ul[kHubUnroll], uw[kHubUnroll];
 #pragma unroll
-            for (int u = 0; u < kHubUnroll; ++u) uw[u] = lane < ul[u] ? lw[u] : INT32_MAX;
+            for (int u = 0; u < kHubUnroll; ++u) {
+                const int32_t q = min(jj + u, 63);
+                ub[u] = __builtin_amdgcn_readlane(dbase, q);
+                ul[u] = jj + u < nch ? __builtin_amdgcn_readlane(dlen, q) : 0;
+            }
+            // unconditional loads at a scalar base and the lane offset: lanes
+            // past a chunk read up to 63 elements further (the column arrays
+            // carry that much slack) and are masked below
+#pragma unroll
+            for (int u = 0; u < kHubUnroll; ++u) uw[u] = (col + ub[u])[(uint32_t)lane];
             unsigned long long hb[kHubUnroll];
             if (MODE == kModeBitmap) {
                 // all chunks' bitmap words first (independent LDS reads), then
-                // ranks and LDS accumulations
+                // bit tests, ranks and LDS accumulations
                 unsigned long long bw[kHubUnroll];
+                uint32_t off[kHubUnroll];
 #pragma unroll
                 for (int u = 0; u < kHubUnroll; ++u) {
-                    const int32_t off = uw[u] <= last ? uw[u] - k - 1 : 0;
-                    bw[u] = reinterpret_cast<const unsigned long long*>(s_bm)[off >> 5];
+                    off[u] = min((uint32_t)(uw[u] - k - 1), guard);
+                    bw[u] = s_bm64[off[u] >> 5];
                 }
 #pragma unroll
                 for (int u = 0; u < kHubUnroll; ++u) {
-                    const int32_t off = uw[u] - k - 1;
-                    const uint32_t bits = (uint32_t)bw[u], bit = (uint32_t)off & 31u;
-                    const bool hit = uw[u] <= last && ((bits >> bit) & 1u);
-                    if (hit) atomicAdd(&s_acc[(uint32_t)(bw[u] >> 32) + __popc(bits & ((1u << bit) - 1u))], 1);
-                    hb[u] = __ballot(hit);
+                    const uint32_t bits = (uint32_t)bw[u];
+                    const uint32_t bit = __builtin_amdgcn_ubfe(bits, off[u], 1u);
+                    // the mask of a lane compare (v_cmp), restricted to the chunk's lanes
+                    const unsigned long long valid = ul[u] >= 64 ? ~0ull : ((1ull << ul[u]) - 1ull);
+                    hb[u] = __builtin_amdgcn_uicmp(bit, 0u, 33 /* ne */) & valid;
+                    if (bit && lane < ul[u])
+                        atomicAdd(&s_acc[(uint32_t)(bw[u] >> 32) + __popc(__builtin_amdgcn_ubfe(bits, 0u, off[u] & 31u))],
+                                  1);
                 }
             } else {
 #pragma unroll
                 for (int u = 0; u < kHubUnroll; ++u) {
                     const int32_t w = uw[u];
                     bool hit = false;
-                    if (w <= last) {  // beyond the last label of row kappa nothing matches
+                    if (lane < ul[u] && w <= last) {  // beyond the last label of row kappa nothing matches
                         int32_t q = -1;
                         if (MODE == kModeKeys) {
                             const int32_t qq = lower_bound_i32(s_keys, d, w);
@@ -235,14 +228,12 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
                     hb[u] = __ballot(hit);
                 }
             }
-            // the chunk's hit word and count go to its lane
+            // the chunk's hit word goes to its lane
 #pragma unroll
             for (int u = 0; u < kHubUnroll; ++u) {
-                const int32_t q = jj + u;
-                if (q < nch && lane == q) {
+                if (lane == jj + u) {
                     word_lo = (uint32_t)hb[u];
                     word_hi = (uint32_t)(hb[u] >> 32);
-                    cnt = __popcll(hb[u]);
                 }
             }
             // S(i, w) of chunks past kHitWords (tails longer than 64 * kHitWords)
@@ -252,16 +243,11 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
                     if (jj + u < nch && ((far >> (jj + u)) & 1ull) && ((hb[u] >> lane) & 1ull))
                         atomicAdd(&x.S[ub[u] + lane], 1);
             }
-#pragma unroll
-            for (int u = 0; u < kHubUnroll; ++u) {
-                ub[u] = nb[u];
-                ul[u] = nl[u];
-                lw[u] = nw[u];
-            }
         }
-        // block end: lane j writes chunk j's hit word and adds its count to S(i, kappa)
-        if (dv && dc < kHitWords)
-            hitw[hit_word_index(de, dc, hit_stride)] = ((unsigned long long)word_hi << 32) | word_lo;
+        // block end: lane j writes chunk j's hit word and adds its hits to S(i, kappa)
+        const unsigned long long word = ((unsigned long long)word_hi << 32) | word_lo;
+        if (dv && dc < kHitWords) hitw[hit_word_index(de, dc, hit_stride)] = word;
+        const int32_t cnt = __popcll(word);
         if (dv && cnt) atomicAdd(&x.S[de], cnt);
     }
 }
@@ -270,7 +256,7 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
                                                            const int32_t* __restrict__ ctail, Ctl* ctl,
                                                            unsigned long long* __restrict__ hitw, int64_t hit_stride,
                                                            unsigned long long* __restrict__ cycles) {
-    __shared__ uint2 s_bm[kSpanWords];   // rank bitmap {bits, set bits before this word}; or keys
+    __shared__ uint2 s_bm[kSpanWords + 1];  // rank bitmap {bits, set bits before this word} + a zero guard word; or keys
     __shared__ int32_t s_acc[kKeyCap];
     __shared__ int s_wave[kHubThreads / 64];
     __shared__ int32_t s_it;
@@ -281,6 +267,7 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
     int32_t* s_keys = reinterpret_cast<int32_t*>(s_bm);
     // Row kappa currently staged in LDS (workgroup-uniform), or cur_k = -1.
     int32_t cur_k = -1, cur_rs = 0, cur_d = 0, cur_last = 0, cur_mode = kModeBitmap;
+    uint32_t cur_guard = 0;
     auto flush = [&]() {  // S(kappa, :) accumulated in LDS -> global
         if (cur_k >= 0 && cur_mode != kModeGlobal)
             for (int32_t q = t; q < cur_d; q += kHubThreads) {
@@ -321,7 +308,8 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
                 __syncthreads();  // the flush and the previous row's tasks are done with LDS
                 if (cur_mode == kModeBitmap) {
                     const int32_t nw = (span + 31) >> 5;
-                    for (int32_t j = t; j < nw; j += kHubThreads) s_bm[j] = make_uint2(0u, 0u);
+                    cur_guard = (uint32_t)nw * 32u;  // labels beyond row kappa read the zero word nw
+                    for (int32_t j = t; j <= nw; j += kHubThreads) s_bm[j] = make_uint2(0u, 0u);
                     __syncthreads();
                     for (int32_t q = t; q < d; q += kHubThreads) {
                         const int32_t off = col[rs + q] - k - 1;
@@ -346,13 +334,13 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
                 __syncthreads();
             }
             if (cur_mode == kModeBitmap)
-                hub_tasks<kModeBitmap>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, cur_rs, cur_d, cur_last,
+                hub_tasks<kModeBitmap>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, cur_rs, cur_d, cur_last, cur_guard,
                                        s_bm, s_acc);
             else if (cur_mode == kModeKeys)
-                hub_tasks<kModeKeys>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, cur_rs, cur_d, cur_last,
+                hub_tasks<kModeKeys>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, cur_rs, cur_d, cur_last, cur_guard,
                                      s_bm, s_acc);
             else
-                hub_tasks<kModeGlobal>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, cur_rs, cur_d, cur_last,
+                hub_tasks<kModeGlobal>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, cur_rs, cur_d, cur_last, cur_guard,
                                        s_bm, s_acc);
             if (cycles) {  // per-row cost samples for the cost model (shader clock)
                 __syncthreads();
