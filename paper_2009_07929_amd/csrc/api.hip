@@ -62,17 +62,17 @@ FullLayout full_layout(int32_t n, int64_t m, int32_t G) {
         L.eid[b] = take(em);
         L.S[b] = take(em);
         L.rowptr[b] = take(vn);
-        L.cedge[b] = take(em);
-        L.csrc[b] = take(em);
-        L.cptr[b] = take(vn);
     }
+    L.cedge = take(em);
+    L.csrc = take(em);
+    L.cptr = take(vn);
     L.xscan = take(em1);
     L.cxscan = take(em1);
     L.blockcnt = take(sizeof(int32_t) * kMaxScanBlocks);
     L.blockoff = take(sizeof(int32_t) * kMaxScanBlocks);
     L.blockcnt2 = take(sizeof(int32_t) * 2 * kMaxScanBlocks);
     L.blockoff2 = take(sizeof(int32_t) * 2 * kMaxScanBlocks);
-    L.tmp_n = take(vn);
+    L.alive_in = take(vn);
     L.itemoff = take(vn);
     L.items = take(sizeof(HubItem) * (size_t)item_capacity(n, m));
     L.ctail = take(em);
@@ -119,9 +119,9 @@ Work carve(void* work, int32_t n, int64_t m, int32_t G) {
         w.b[b].eid = (int32_t*)(base + L.eid[b]);
         w.b[b].S = (int32_t*)(base + L.S[b]);
         w.b[b].rowptr = (int32_t*)(base + L.rowptr[b]);
-        w.c[b].edge = (int32_t*)(base + L.cedge[b]);
-        w.c[b].src = (int32_t*)(base + L.csrc[b]);
-        w.c[b].ptr = (int32_t*)(base + L.cptr[b]);
+        w.c[b].edge = (int32_t*)(base + L.cedge);  // one set of in-edge lists, remapped in place
+        w.c[b].src = (int32_t*)(base + L.csrc);
+        w.c[b].ptr = (int32_t*)(base + L.cptr);
     }
     w.sc.xscan = (int32_t*)(base + L.xscan);
     w.sc.cxscan = (int32_t*)(base + L.cxscan);
@@ -129,7 +129,7 @@ Work carve(void* work, int32_t n, int64_t m, int32_t G) {
     w.sc.blockoff = (int32_t*)(base + L.blockoff);
     w.sc.blockcnt2 = (int32_t*)(base + L.blockcnt2);
     w.sc.blockoff2 = (int32_t*)(base + L.blockoff2);
-    w.sc.tmp_n = (int32_t*)(base + L.tmp_n);
+    w.sc.alive_in = (int32_t*)(base + L.alive_in);
     w.sc.itemoff = (int32_t*)(base + L.itemoff);
     w.sc.items = (HubItem*)(base + L.items);
     w.sc.ctail = (int32_t*)(base + L.ctail);

@@ -51,6 +51,7 @@ struct Ctl {
     int32_t item_next;   // next hub item to take (persistent hub kernel)
     int32_t n_active;    // rows with support work in the current pass (learned schedule, sampling)
     int32_t n_samples;   // cost-model samples written so far
+    int32_t csc_m;       // in-edge list entries (alive edges + tombstones of removed ones)
     int64_t removed_total;
 };
 
@@ -65,8 +66,11 @@ struct Buf {
     int32_t* rowptr;
 };
 
-// In-edge lists of a buffer: for every row kappa, the positions of the edges
-// whose column is kappa (edge[ptr[kappa] .. ptr[kappa+1])) and their rows.
+// In-edge lists: for every row kappa, the positions of the edges whose column
+// is kappa (edge[ptr[kappa] .. ptr[kappa+1])) and their rows.  Built once per
+// run; after every prune the positions are remapped in place and the entries
+// of removed edges become tombstones (edge = -1), so the lists keep their
+// length (Ctl::csc_m) for the whole run.
 struct Csc {
     int32_t* edge;
     int32_t* src;
@@ -87,7 +91,7 @@ struct Scratch {
     int32_t* blockoff;    // int32[kMaxScanBlocks]
     int32_t* blockcnt2;   // int32[2*kMaxScanBlocks]
     int32_t* blockoff2;   // int32[2*kMaxScanBlocks]
-    int32_t* tmp_n;       // int32[n]
+    int32_t* alive_in;    // int32[n+1]: alive in-edges per row kappa (the lists also hold tombstones)
     int32_t* itemoff;     // int32[n+1]
     HubItem* items;       // HubItem[item capacity]
     int32_t* ctail;       // int32[m]: tail length of the task of every in-edge list entry
@@ -128,8 +132,8 @@ __host__ __device__ inline int64_t hit_word_index(int32_t e, int32_t c, int64_t 
 
 struct Layout {
     size_t col[2], src[2], eid[2], S[2], rowptr[2];
-    size_t cedge[2], csrc[2], cptr[2];
-    size_t xscan, cxscan, blockcnt, blockoff, blockcnt2, blockoff2, tmp_n, itemoff, items, ctail,
+    size_t cedge, csrc, cptr;
+    size_t xscan, cxscan, blockcnt, blockoff, blockcnt2, blockoff2, alive_in, itemoff, items, ctail,
         is_hub, hub_row, hitw, wave_tasks, thread_tasks, insum, cycles, act_off, act_list, feats, pred, chunk_sz,
         rs_hist;
     size_t ctl;        // Ctl

@@ -4,8 +4,8 @@
 // 1-p: a keep flag per element, a per-workgroup count, one workgroup scanning
 // the counts, then a scatter whose positions come from a wave ballot + mbcnt
 // prefix and the wave totals.  Every old position's new position is recorded
-// (xscan) so that row pointers, and the in-edge lists that point at edge
-// positions, can be remapped without another search.
+// (xscan; ~q for a dropped element) so that row pointers, and the in-edge
+// lists that point at edge positions, can be remapped without another search.
 #include "device_util.h"
 #include "kernels.h"
 
@@ -31,9 +31,11 @@ struct CsrRound {
     Buf x, y;
     int32_t thr;
     BatchCtx b;
+    int32_t* alive_in;  // alive in-edges per row (in-edge lists kept), or null
     __device__ int32_t load(int32_t e) const { return e; }
     __device__ bool keep(int32_t e) const { return round_keep(x, b, thr, e); }
     __device__ void drop(int32_t e, int32_t) const {
+        if (alive_in) atomicSub(&alive_in[x.col[e]], 1);
         if (b.thrv && b.done_now[b.gidv[x.src[e]]]) {
             const int32_t c = x.eid[e];
             b.mask[c] = 1;
@@ -52,30 +54,17 @@ struct CsrRound {
 struct CsrAlive {
     Buf x, y;
     const uint8_t* alive_can;
+    int32_t* alive_in;  // alive in-edges per row (in-edge lists kept), or null
     __device__ int32_t load(int32_t e) const { return e; }
     __device__ bool keep(int32_t e) const { return alive_can[x.eid[e]] != 0; }
-    __device__ void drop(int32_t, int32_t) const {}
+    __device__ void drop(int32_t e, int32_t) const {
+        if (alive_in) atomicSub(&alive_in[x.col[e]], 1);
+    }
     __device__ void emit(int32_t e, int32_t, int32_t q) const {
         y.col[q] = x.col[e];
         y.src[q] = x.src[e];
         y.eid[q] = x.eid[e];
         y.S[q] = 0;
-    }
-};
-
-// In-edge list entry c (an edge position of buffer x); it survives with its
-// edge and is rewritten to that edge's new position.  Runs after the CSR
-// filter, whose xscan holds q for a kept edge and ~q for a dropped one, so one
-// read decides and remaps.
-struct CscEntry {
-    Csc cx, cy;
-    const int32_t* xscan;
-    __device__ int32_t load(int32_t c) const { return xscan[cx.edge[c]]; }
-    __device__ bool keep(int32_t v) const { return v >= 0; }
-    __device__ void drop(int32_t, int32_t) const {}
-    __device__ void emit(int32_t v, int32_t c, int32_t q) const {
-        cy.edge[q] = v;
-        cy.src[q] = cx.src[c];
     }
 };
 
@@ -188,6 +177,22 @@ __global__ __launch_bounds__(kBlock) void k_ptr_remap(const int32_t* __restrict_
     new_ptr[s] = v < 0 ? ~v : v;
 }
 
+// In-edge lists after the CSR filter, in place: every entry's edge position
+// becomes the edge's new position (xscan holds q for a kept edge, ~q for a
+// removed one); entries of removed edges, and tombstones, stay -1.
+__global__ __launch_bounds__(kBlock) void k_csc_remap(int32_t* __restrict__ cedge, const int32_t* __restrict__ xscan,
+                                                    const Ctl* __restrict__ ctl, int round) {
+    if (round && ctl->done) return;
+    const int32_t N = ctl->csc_m;
+    for (int32_t c = (int32_t)(blockIdx.x * kBlock + threadIdx.x); c < N; c += (int32_t)(gridDim.x * kBlock)) {
+        const int32_t e = cedge[c];
+        if (e >= 0) {
+            const int32_t v = xscan[e];
+            cedge[c] = v >= 0 ? v : -1;
+        }
+    }
+}
+
 // Batched form: the run ends after the pass that leaves no edge.
 __global__ void k_batch_end(Ctl* ctl, int p) {
     if (threadIdx.x == 0 && !ctl->done && ctl->m_buf[1 - p] == 0) {
@@ -219,16 +224,17 @@ hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* 
                           hipStream_t s) {
     const int round = mode == 0;
     const bool batch = b.thrv != nullptr;
+    int32_t* alive_in = cx ? sc.alive_in : nullptr;
     if (mode == 0) {
-        run_filter(CsrRound{x, y, thr, b}, ctl, p, batch ? 3 : 1, 1, sc.blockcnt, sc.blockoff, sc.xscan, m_hint, s);
+        run_filter(CsrRound{x, y, thr, b, alive_in}, ctl, p, batch ? 3 : 1, 1, sc.blockcnt, sc.blockoff, sc.xscan,
+                   m_hint, s);
     } else {
-        run_filter(CsrAlive{x, y, alive_can}, ctl, p, 2, 0, sc.blockcnt, sc.blockoff, sc.xscan, m_hint, s);
+        run_filter(CsrAlive{x, y, alive_can, alive_in}, ctl, p, 2, 0, sc.blockcnt, sc.blockoff, sc.xscan, m_hint, s);
     }
     k_ptr_remap<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(x.rowptr, y.rowptr, n, sc.xscan, ctl, round);
-    if (cx && cy) {
-        run_filter(CscEntry{*cx, *cy, sc.xscan}, ctl, p, 0, round, sc.blockcnt, sc.blockoff, sc.cxscan, m_hint, s);
-        k_ptr_remap<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(cx->ptr, cy->ptr, n, sc.cxscan, ctl, round);
-    }
+    if (cx && m_hint > 0)  // the in-edge lists (remapped in place; cy is the same set)
+        k_csc_remap<<<min(grid_for(m_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(cx->edge, sc.xscan, ctl, round);
+    (void)cy;
     if (batch && mode == 0) k_batch_end<<<1, 64, 0, s>>>(ctl, p);
     return hipGetLastError();
 }

@@ -199,18 +199,27 @@ __global__ __launch_bounds__(kBlock) void k_csc_rows(const int32_t* __restrict__
 }
 
 // Tail length of the task of every in-edge list entry of the pass: the part
-// of row i after the edge (Algorithm 3's a12(j+1:)).  Also clears the first
-// hit word of every edge, so that tasks the hub kernel does not run read as
-// having no hits.
+// of row i after the edge (Algorithm 3's a12(j+1:)); 0 for a tombstone.  Also
+// clears the first hit word of every alive edge, so that tasks the hub kernel
+// does not run read as having no hits.
 __global__ __launch_bounds__(kBlock) void k_task_tails(Buf x, Csc c, const Ctl* __restrict__ ctl, int p,
                                                      int32_t* __restrict__ ctail,
                                                      unsigned long long* __restrict__ hitw) {
     if (ctl->done) return;
-    const int32_t m = ctl->m_buf[p];
-    for (int32_t q = (int32_t)(blockIdx.x * kBlock + threadIdx.x); q < m; q += (int32_t)(gridDim.x * kBlock)) {
-        ctail[q] = x.rowptr[c.src[q] + 1] - c.edge[q] - 1;
-        hitw[hit_word_index(q, 0, 0)] = 0ull;
+    const int32_t nc = ctl->csc_m, m = ctl->m_buf[p];
+    for (int32_t q = (int32_t)(blockIdx.x * kBlock + threadIdx.x); q < nc; q += (int32_t)(gridDim.x * kBlock)) {
+        const int32_t e = c.edge[q];
+        ctail[q] = e < 0 ? 0 : x.rowptr[c.src[q] + 1] - e - 1;
+        if (q < m) hitw[hit_word_index(q, 0, 0)] = 0ull;
     }
+}
+
+// Alive in-edges of every row kappa at the start of a run: the list lengths.
+// The prune decrements them for every removed edge.
+__global__ __launch_bounds__(kBlock) void k_alive_in_init(const int32_t* __restrict__ cptr, int32_t n,
+                                                        int32_t* __restrict__ alive_in) {
+    const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (k < n) alive_in[k] = cptr[k + 1] - cptr[k];
 }
 
 // ---- hub items
@@ -219,6 +228,7 @@ __global__ __launch_bounds__(kBlock) void k_task_tails(Buf x, Csc c, const Ctl* 
 struct HubChunks {
     const int32_t* rowptr;
     const int32_t* cptr;
+    const int32_t* alive_in;  // alive in-edges per row (the lists also hold tombstones)
     const uint8_t* is_hub;    // per row, or null = every row with work
     const int32_t* chunk_sz;  // tasks per item of each row (<= kHubChunk), or null = chunk_all
     int32_t chunk_all;
@@ -226,7 +236,7 @@ struct HubChunks {
     __device__ int32_t operator()(int32_t k) const {
         const int32_t indeg = cptr[k + 1] - cptr[k];
         const int32_t d = rowptr[k + 1] - rowptr[k];
-        if (indeg == 0 || d == 0) return 0;
+        if (alive_in[k] == 0 || d == 0) return 0;
         if (is_hub && !is_hub[k]) return 0;
         const int32_t cs = size(k);
         return (indeg + cs - 1) / cs;
@@ -267,9 +277,9 @@ __global__ __launch_bounds__(kBlock) void k_hub_items(HubChunks f, const int32_t
 // non-empty row).
 struct ActiveRow {
     const int32_t* rowptr;
-    const int32_t* cptr;
+    const int32_t* alive_in;  // alive in-edges per row
     __device__ int32_t operator()(int32_t k) const {
-        return (cptr[k + 1] > cptr[k] && rowptr[k + 1] > rowptr[k]) ? 1 : 0;
+        return (alive_in[k] > 0 && rowptr[k + 1] > rowptr[k]) ? 1 : 0;
     }
 };
 
@@ -389,13 +399,13 @@ __global__ void k_advance_samples(Ctl* ctl, int32_t capacity) {
 // ---- static degree heuristic: which rows kappa are hub rows
 
 __global__ __launch_bounds__(kBlock) void k_heuristic_bins(const int32_t* __restrict__ rowptr,
-                                                         const int32_t* __restrict__ cptr, int32_t n,
+                                                         const int32_t* __restrict__ alive_in, int32_t n,
                                                          int32_t hub_min_in, uint8_t* __restrict__ is_hub,
                                                          const Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k >= n) return;
-    const int32_t indeg = cptr[k + 1] - cptr[k];
+    const int32_t indeg = alive_in[k];
     const int32_t d = rowptr[k + 1] - rowptr[k];
     is_hub[k] = (d > 0 && indeg >= hub_min_in) ? 1 : 0;
 }
@@ -411,6 +421,7 @@ struct TaskClass {
     int32_t wave_min;
     __device__ int cls(int32_t i) const {
         const int32_t e = c.edge[i];
+        if (e < 0) return 0;  // tombstone of a removed edge
         const int32_t k = x.col[e];
         if (is_hub[k]) return 0;
         const int32_t tail = x.rowptr[c.src[i] + 1] - e - 1;
@@ -425,7 +436,7 @@ __global__ __launch_bounds__(kBlock) void k_task_count(TaskClass tc, const Ctl* 
     __shared__ int s_wave[kBlock / 64];
     if (ctl->done) return;
     int32_t lo, hi;
-    span_of(ctl->m_buf[p], lo, hi);
+    span_of(ctl->csc_m, lo, hi);
     int a = 0, b = 0;
     for (int32_t i = lo + (int32_t)threadIdx.x; i < hi; i += kBlock) {
         const int k = tc.cls(i);
@@ -479,7 +490,7 @@ __global__ __launch_bounds__(kBlock) void k_task_scatter(TaskClass tc, const Ctl
     __shared__ int s_wave[kBlock / 64];
     if (ctl->done) return;
     int32_t lo, hi;
-    span_of(ctl->m_buf[p], lo, hi);
+    span_of(ctl->csc_m, lo, hi);
     int32_t ba = off2[blockIdx.x], bb = off2[kMaxScanBlocks + blockIdx.x];
     for (int32_t t0 = lo; t0 < hi; t0 += kBlock) {
         const int32_t i = t0 + (int32_t)threadIdx.x;
@@ -501,6 +512,7 @@ __global__ __launch_bounds__(kBlock) void k_task_scatter(TaskClass tc, const Ctl
 hipError_t launch_build_csc(const Buf& b, const Csc& c, int32_t n, int32_t m, Scratch& sc, hipStream_t s) {
     if (m == 0) {
         k_fill_i32<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(c.ptr, n + 1, 0);
+        k_fill_i32<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(sc.alive_in, n + 1, 0);
         return hipGetLastError();
     }
     int bits = 0;
@@ -524,6 +536,7 @@ hipError_t launch_build_csc(const Buf& b, const Csc& c, int32_t n, int32_t m, Sc
     }
     k_col_ptr<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(kin, m, n, c.ptr);
     k_csc_rows<<<grid_for(m), kBlock, 0, s>>>(b.src, c.edge, m, c.src);
+    k_alive_in_init<<<grid_for(n), kBlock, 0, s>>>(c.ptr, n, sc.alive_in);
     return hipGetLastError();
 }
 
@@ -547,15 +560,19 @@ hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched,
     const uint8_t* is_hub = nullptr;
     const int32_t* chunk = nullptr;
     const bool learned = sched == KTRUSS_SCHED_LEARNED && mlp;
+    // task tails (the in-edge lists hold tombstones of removed edges)
+    if (m_hint > 0)
+        k_task_tails<<<min(grid_for(m0), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, c, ctl, p, sc.ctail, sc.hitw);
     if (sched == KTRUSS_SCHED_HEURISTIC || (sched == KTRUSS_SCHED_LEARNED && !mlp)) {
         const int32_t hub_min_in = t.hub_min_work > 0 ? t.hub_min_work : kDefaultHubMinIn;
-        k_heuristic_bins<<<grid_for(n), kBlock, 0, s>>>(x.rowptr, c.ptr, n, hub_min_in, sc.is_hub, ctl);
+        k_heuristic_bins<<<grid_for(n), kBlock, 0, s>>>(x.rowptr, sc.alive_in, n, hub_min_in, sc.is_hub, ctl);
         is_hub = sc.is_hub;
     }
     if (learned || features) {
         // rows with work, their features (and, learned, the cost model's bins)
-        device_scan(ActiveRow{x.rowptr, c.ptr}, n, ctl, sc, sc.act_off, &ctl->n_active, s);
-        k_active_list<<<grid_for(n), kBlock, 0, s>>>(ActiveRow{x.rowptr, c.ptr}, n, sc.act_off, sc.act_list, ctl);
+        device_scan(ActiveRow{x.rowptr, sc.alive_in}, n, ctl, sc, sc.act_off, &ctl->n_active, s);
+        k_active_list<<<grid_for(n), kBlock, 0, s>>>(ActiveRow{x.rowptr, sc.alive_in}, n, sc.act_off, sc.act_list,
+                                                      ctl);
         k_row_features<<<grid_for(n), kBlock, 0, s>>>(x.rowptr, sc.insum, sc.act_list, ctl, p, m0, sc.feats);
     }
     if (learned) {
@@ -572,12 +589,9 @@ hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched,
     // hub items (every row with work under FORCE_HUB)
     int32_t chunk_all = t.hub_chunk_tasks > 0 ? t.hub_chunk_tasks : kHubChunk;
     chunk_all = max(kMinLearnedChunk, min(chunk_all, kHubChunk));  // item capacity assumes >= kMinLearnedChunk
-    HubChunks hc{x.rowptr, c.ptr, is_hub, chunk, chunk_all};
+    HubChunks hc{x.rowptr, c.ptr, sc.alive_in, is_hub, chunk, chunk_all};
     device_scan(hc, n, ctl, sc, sc.itemoff, &ctl->n_items, s);
     k_hub_items<<<grid_for(n), kBlock, 0, s>>>(hc, x.col, n, sc.itemoff, sc.items, sc.hub_row, ctl);
-    if (m_hint > 0)
-        k_task_tails<<<min(grid_for(m_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, c, ctl, p, sc.ctail,
-                                                                                        sc.hitw);
     if (is_hub) {
         const int32_t wave_min = t.wave_min_work > 0 ? t.wave_min_work : kDefaultWaveMin;
         TaskClass tc{x, c, is_hub, wave_min};

@@ -21,6 +21,7 @@ __global__ void k_ctl_reset(Ctl* ctl, int32_t m) {
         ctl->item_next = 0;
         ctl->n_active = 0;
         ctl->n_samples = 0;
+        ctl->csc_m = m;
         ctl->removed_total = 0;
     }
 }
