@@ -424,7 +424,7 @@ int32_t enqueue_round(const RunSpec& r, Work& w, int p, const PassDims& dm, hipS
     if (r.G > 0) HIP_TRY(launch_batch_status(w.b[p], w.batch, r.G, r.K, r.rounds_dev, w.ctl, s), "batch status");
     const bool csc = uses_csc(r.sched);
     HIP_TRY(launch_compact(w.b[p], w.b[1 - p], csc ? &w.c[p] : nullptr, csc ? &w.c[1 - p] : nullptr, r.n, 0, r.thr,
-                           nullptr, w.batch, w.sc, w.ctl, p, dm.m, s),
+                           nullptr, w.batch, w.sc, w.ctl, p, dm.m, r.m, s),
             "prune launch");
     return prepare(r, w, 1 - p, dm.m, s);
 }
@@ -648,7 +648,7 @@ int32_t ktruss_support(const ktruss_graph* g, const uint8_t* alive, int32_t* sup
     int p = 0;
     if (alive) {
         HIP_TRY(launch_compact(w.b[0], w.b[1], csc ? &w.c[0] : nullptr, csc ? &w.c[1] : nullptr, n, 1, 0, alive,
-                               w.batch, w.sc, w.ctl, 0, m, s),
+                               w.batch, w.sc, w.ctl, 0, m, m, s),
                 "restrict to alive");
         p = 1;
         HIP_TRY(launch_set_final(w.ctl, 1, s), "final buffer");

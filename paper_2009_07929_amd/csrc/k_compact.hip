@@ -221,7 +221,7 @@ void run_filter(const P& pol, Ctl* ctl, int p, int update, int round, int32_t* b
 
 hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* cy, int32_t n, int mode, int32_t thr,
                           const uint8_t* alive_can, const BatchCtx& b, Scratch& sc, Ctl* ctl, int p, int32_t m_hint,
-                          hipStream_t s) {
+                          int32_t csc_hint, hipStream_t s) {
     const int round = mode == 0;
     const bool batch = b.thrv != nullptr;
     int32_t* alive_in = cx ? sc.alive_in : nullptr;
@@ -232,8 +232,9 @@ hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* 
         run_filter(CsrAlive{x, y, alive_can, alive_in}, ctl, p, 2, 0, sc.blockcnt, sc.blockoff, sc.xscan, m_hint, s);
     }
     k_ptr_remap<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(x.rowptr, y.rowptr, n, sc.xscan, ctl, round);
-    if (cx && m_hint > 0)  // the in-edge lists (remapped in place; cy is the same set)
-        k_csc_remap<<<min(grid_for(m_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(cx->edge, sc.xscan, ctl, round);
+    if (cx && csc_hint > 0)  // the in-edge lists (remapped in place; cy is the same set)
+        k_csc_remap<<<min(grid_for(csc_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(cx->edge, sc.xscan, ctl,
+                                                                                         round);
     (void)cy;
     if (batch && mode == 0) k_batch_end<<<1, 64, 0, s>>>(ctl, p);
     return hipGetLastError();

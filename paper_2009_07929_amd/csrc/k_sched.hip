@@ -595,7 +595,7 @@ hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched,
     if (is_hub) {
         const int32_t wave_min = t.wave_min_work > 0 ? t.wave_min_work : kDefaultWaveMin;
         TaskClass tc{x, c, is_hub, wave_min};
-        const int32_t G = scan_grid(m_hint);
+        const int32_t G = scan_grid(m0);  // the in-edge lists keep the run's m entries
         k_task_count<<<G, kBlock, 0, s>>>(tc, ctl, p, sc.blockcnt2);
         k_task_scan<<<1, kScanThreads, 0, s>>>(sc.blockcnt2, sc.blockoff2, G, ctl);
         k_task_scatter<<<G, kBlock, 0, s>>>(tc, ctl, p, sc.blockoff2, sc.wave_tasks, sc.thread_tasks);

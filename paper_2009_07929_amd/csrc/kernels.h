@@ -24,10 +24,11 @@ hipError_t launch_prune_canonical(const int32_t* support, uint8_t* alive, int32_
 // given.
 // With a batch context (b.thrv set) the threshold is per vertex, edges of
 // graphs finished in this pass are written to the outputs and dropped, and
-// the run ends when no edge is left.
+// the run ends when no edge is left.  m_hint bounds the alive edges, csc_hint
+// the in-edge list entries (the run's m: removed edges stay as tombstones).
 hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* cy, int32_t n, int mode, int32_t thr,
                           const uint8_t* alive_can, const BatchCtx& b, Scratch& sc, Ctl* ctl, int p, int32_t m_hint,
-                          hipStream_t s);
+                          int32_t csc_hint, hipStream_t s);
 
 // ---- batched form (k_batch.hip)
 hipError_t launch_batch_setup(const BatchCtx& b, int32_t G, int32_t n_total, const int32_t* K, const int32_t* src,
