@@ -64,9 +64,12 @@ typedef struct ktruss_tuning {
     int32_t hub_chunk_work;  /* learned: predicted shader cycles per hub item when a hub row is split */
     int32_t rounds_per_sync; /* <= 1: host checks the fixpoint after every round (exact grids);
                                 >= 2: rounds are captured in a hipGraph and replayed this many at a time */
-    float learned_hub_min;   /* learned: rows whose predicted log2 cycles reach this are hub rows */
+    float learned_hub_min;   /* learned: rows whose predicted log2 cycles reach this are hub rows (0: 12) */
     int32_t hub_chunk_tasks; /* heuristic/force-hub: tasks per hub item (clamped to 16..256) */
-    int32_t reserved[2];
+    int32_t plain_max_work;  /* heuristic/learned: if the input's mean merge length per edge (row tail + row
+                                kappa) is at most this, ktruss_run/ktruss_support use thread-per-edge for
+                                every task and build no in-edge lists; 0: default 32, negative: never */
+    int32_t reserved[1];
 } ktruss_tuning;
 
 /* Cost model: 5 inputs -> 64 ReLU -> 64 ReLU -> 1 output, FP32.  Parameter

@@ -1,9 +1,10 @@
 """Autotuner of the support schedule and its tile parameters.
 
-Searches, by timed runs on the device, the schedule (hub, heuristic, learned)
-and the knobs of ktruss_tuning: tasks per hub item, the hub-row threshold of
-the heuristic, the wavefront/thread cut-off, the learned split target and the
-number of prune rounds replayed from a hipGraph per host check.  Results are
+Searches, by timed runs on the device, the schedule (hub, heuristic, learned,
+plain) and the knobs of ktruss_tuning: tasks per hub item, the hub-row
+threshold of the heuristic, the wavefront/thread cut-off, the learned split
+target, the light-graph gate and the number of prune rounds replayed from a
+hipGraph per host check.  Results are
 keyed by (graph class, K) and cached in a JSON file; a cached entry is reused
 for any graph of the same class.  Every candidate produces identical results
 (the schedule never changes the truss), so only time is compared.
@@ -26,21 +27,23 @@ SCHEDULE_IDS = {"plain": kt.SCHED_PLAIN, "heuristic": kt.SCHED_HEURISTIC, "learn
                 "hub": kt.SCHED_FORCE_HUB}
 
 DEFAULT = {"schedule": "hub", "hub_chunk_tasks": 256, "hub_min_work": 8, "wave_min_work": 192,
-           "hub_chunk_work": 400000, "learned_hub_min": 16.0, "rounds_per_sync": 0}
+           "hub_chunk_work": 400000, "learned_hub_min": 12.0, "rounds_per_sync": 0, "plain_max_work": 0}
 
 # values tried per knob (coordinate search, in this order)
 SPACE = [
-    ("schedule", ["hub", "heuristic", "learned"]),
+    ("schedule", ["hub", "heuristic", "learned", "plain"]),
     ("hub_chunk_tasks", [64, 128, 256]),
     ("rounds_per_sync", [0, 4, 16]),
     ("hub_min_work", [2, 8, 32]),
     ("wave_min_work", [64, 192, 768]),
-    ("learned_hub_min", [12.0, 16.0, 20.0]),
+    ("learned_hub_min", [8.0, 12.0, 16.0]),
     ("hub_chunk_work", [100000, 400000, 1600000]),
+    ("plain_max_work", [-1, 0, 128]),
 ]
 # knobs that only matter under some schedules
 RELEVANT = {"hub_min_work": {"heuristic"}, "wave_min_work": {"heuristic", "learned"},
-            "learned_hub_min": {"learned"}, "hub_chunk_work": {"learned"}, "hub_chunk_tasks": {"hub", "heuristic"}}
+            "learned_hub_min": {"learned"}, "hub_chunk_work": {"learned"}, "hub_chunk_tasks": {"hub", "heuristic"},
+            "plain_max_work": {"heuristic", "learned"}, "rounds_per_sync": {"hub", "heuristic", "learned", "plain"}}
 
 
 def graph_class(rowptr) -> str:
@@ -65,6 +68,7 @@ def to_tuning(cfg) -> kt.ktruss_tuning:
     t.hub_chunk_work = int(cfg["hub_chunk_work"])
     t.learned_hub_min = float(cfg["learned_hub_min"])
     t.rounds_per_sync = int(cfg["rounds_per_sync"])
+    t.plain_max_work = int(cfg.get("plain_max_work", 0))
     return t
 
 

@@ -195,12 +195,16 @@ int32_t check_graph(const ktruss_graph* g, bool need_work) {
     } while (0)
 
 // Validates the input CSR on the device (writing each edge's row into
-// src_out) and reads the verdict back.  Synchronises s.
+// src_out) and reads the verdict back.  Synchronises s.  merge_work: if not
+// null, receives the input's merge length summed over its edges.
 int32_t validate_on_device(const int32_t* rowptr, const int32_t* col, int32_t n, int32_t m, const Work& w,
-                           int32_t* src_out, hipStream_t s) {
-    HIP_TRY(launch_validate(rowptr, col, n, m, src_out, w.ctl, s), "validate launch");
+                           int32_t* src_out, hipStream_t s, unsigned long long* merge_work = nullptr) {
+    HIP_TRY(launch_validate(rowptr, col, n, m, src_out, w.ctl, merge_work != nullptr, s), "validate launch");
     int32_t err = 0;
     HIP_TRY(hipMemcpyAsync(&err, &w.ctl->err, sizeof(err), hipMemcpyDeviceToHost, s), "validate readback");
+    if (merge_work)
+        HIP_TRY(hipMemcpyAsync(merge_work, &w.ctl->merge_work, sizeof(*merge_work), hipMemcpyDeviceToHost, s),
+                "merge work readback");
     HIP_TRY(hipStreamSynchronize(s), "validate sync");
     if (err)
         return fail(KTRUSS_E_INVALID,
@@ -301,6 +305,20 @@ unsigned long long* profile_work() {
 }
 
 bool uses_csc(int sched) { return sched != KTRUSS_SCHED_PLAIN && sched != KTRUSS_SCHED_FORCE_WAVE; }
+
+// Light-graph gate of the heuristic and learned schedules: an input whose
+// mean merge length per edge is at most plain_max_work (0: the default,
+// negative: never) has no task long enough to pay for in-edge lists, staging
+// or binning, so the run is thread-per-edge throughout.
+bool gated(const ktruss_graph* g) {
+    return (g->schedule == KTRUSS_SCHED_HEURISTIC || g->schedule == KTRUSS_SCHED_LEARNED) &&
+           g->tuning.plain_max_work >= 0;
+}
+int schedule_for(const ktruss_graph* g, unsigned long long merge_work) {
+    if (!gated(g)) return g->schedule;
+    const unsigned long long t = g->tuning.plain_max_work > 0 ? g->tuning.plain_max_work : kDefaultPlainMaxWork;
+    return merge_work <= t * (unsigned long long)g->m ? KTRUSS_SCHED_PLAIN : g->schedule;
+}
 
 // Grid sizes of one pass: exact counts in host-loop mode, upper bounds when
 // the pass is captured in a graph (the kernels read the true counts).
@@ -637,10 +655,11 @@ int32_t ktruss_support(const ktruss_graph* g, const uint8_t* alive, int32_t* sup
     hipStream_t s = (hipStream_t)stream;
     Work w = carve(g->work, g->n, g->m, 0);
     const int32_t n = g->n, m = (int32_t)g->m;
-    rc = validate_on_device(g->rowptr, g->col, n, m, w, w.b[0].src, s);
+    unsigned long long merge_work = 0;
+    rc = validate_on_device(g->rowptr, g->col, n, m, w, w.b[0].src, s, gated(g) ? &merge_work : nullptr);
     if (rc != KTRUSS_OK) return rc;
     if (m == 0) return KTRUSS_OK;
-    const RunSpec r = make_spec(n, m, g->rowptr, g->col, g->schedule, g->tuning, g->mlp_params);
+    const RunSpec r = make_spec(n, m, g->rowptr, g->col, schedule_for(g, merge_work), g->tuning, g->mlp_params);
     const bool csc = uses_csc(r.sched);
     rc = set_up_run(r, w, s);
     if (rc != KTRUSS_OK) return rc;
@@ -687,13 +706,14 @@ int32_t ktruss_run(const ktruss_graph* g, int32_t K, uint8_t* mask, int32_t* sup
     hipStream_t s = (hipStream_t)stream;
     Work w = carve(g->work, g->n, g->m, 0);
     const int32_t n = g->n, m = (int32_t)g->m;
-    rc = validate_on_device(g->rowptr, g->col, n, m, w, w.b[0].src, s);
+    unsigned long long merge_work = 0;
+    rc = validate_on_device(g->rowptr, g->col, n, m, w, w.b[0].src, s, gated(g) ? &merge_work : nullptr);
     if (rc != KTRUSS_OK) return rc;
     if (m == 0) {
         if (rounds) *rounds = 1;
         return KTRUSS_OK;
     }
-    RunSpec r = make_spec(n, m, g->rowptr, g->col, g->schedule, g->tuning, g->mlp_params);
+    RunSpec r = make_spec(n, m, g->rowptr, g->col, schedule_for(g, merge_work), g->tuning, g->mlp_params);
     r.thr = K - 2;
     rc = set_up_run(r, w, s);
     if (rc != KTRUSS_OK) return rc;

@@ -28,7 +28,8 @@ constexpr int kRsTile = 4096;            // (column, edge) pairs per workgroup o
 constexpr int kHitWords = 8;             // 64-bit hit words per task: tail offsets below 512 (see k_support_hub)
 
 // learned schedule defaults (predicted log2 shader cycles of a row's hub work)
-constexpr float kDefaultLearnedHubMin = 16.0f;
+constexpr float kDefaultLearnedHubMin = 12.0f;
+constexpr int32_t kDefaultPlainMaxWork = 32;
 constexpr float kDefaultLearnedChunk = 400000.0f;
 constexpr int kMinLearnedChunk = 16;     // fewest tasks per hub item
 
@@ -53,6 +54,7 @@ struct Ctl {
     int32_t n_samples;   // cost-model samples written so far
     int32_t csc_m;       // in-edge list entries (alive edges + tombstones of removed ones)
     int64_t removed_total;
+    unsigned long long merge_work;  // input's merge length summed over its edges (row tail + row kappa)
 };
 
 // One buffer of the working graph: the alive edges compacted in canonical

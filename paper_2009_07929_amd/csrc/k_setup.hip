@@ -22,6 +22,7 @@ __global__ void k_ctl_reset(Ctl* ctl, int32_t m) {
         ctl->n_active = 0;
         ctl->n_samples = 0;
         ctl->csc_m = m;
+        ctl->merge_work = 0ull;
         ctl->removed_total = 0;
     }
 }
@@ -48,30 +49,42 @@ __global__ __launch_bounds__(kBlock) void k_validate_rowptr(const int32_t* __res
 // checked monotone) and walks on, so long rows cost no more than short ones.
 constexpr int kValSpan = 16;
 
+// tally: also sums every edge's merge length (the tail of its row after it
+// plus the length of row kappa = its column) into ctl->merge_work, the input
+// statistic of the light-graph gate.
 __global__ __launch_bounds__(kBlock) void k_validate_rows(const int32_t* __restrict__ rowptr,
                                                         const int32_t* __restrict__ col, int32_t n, int32_t m,
-                                                        int32_t* __restrict__ src_out, Ctl* ctl) {
+                                                        int32_t* __restrict__ src_out, Ctl* ctl, bool tally) {
     if (ctl->err) return;
     const int64_t p0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kValSpan;
-    if (p0 >= m) return;
-    // row = last i with rowptr[i] <= p0
-    int32_t lo = 0, hi = n;  // rowptr[lo] <= p0 < rowptr[hi]
-    while (hi - lo > 1) {
-        const int32_t mid = lo + ((hi - lo) >> 1);
-        if (rowptr[mid] <= p0) lo = mid;
-        else hi = mid;
+    unsigned long long work = 0ull;
+    if (p0 < m) {
+        // row = last i with rowptr[i] <= p0
+        int32_t lo = 0, hi = n;  // rowptr[lo] <= p0 < rowptr[hi]
+        while (hi - lo > 1) {
+            const int32_t mid = lo + ((hi - lo) >> 1);
+            if (rowptr[mid] <= p0) lo = mid;
+            else hi = mid;
+        }
+        int32_t row = lo, next = rowptr[row + 1];
+        const int32_t p1 = (int32_t)min(p0 + kValSpan, (int64_t)m);
+        int bad = 0;
+        for (int32_t p = (int32_t)p0; p < p1; ++p) {
+            while (p >= next) next = rowptr[++row + 1];
+            const int32_t prev = p == rowptr[row] ? row : col[p - 1];
+            const int32_t c = col[p];
+            const bool b = (c <= prev) | (c >= n);
+            bad |= b;
+            src_out[p] = row;
+            if (tally && !b) work += (unsigned long long)(next - p - 1 + rowptr[c + 1] - rowptr[c]);
+        }
+        if (bad) atomicOr(&ctl->err, 16);
     }
-    int32_t row = lo, next = rowptr[row + 1];
-    const int32_t p1 = (int32_t)min(p0 + kValSpan, (int64_t)m);
-    int bad = 0;
-    for (int32_t p = (int32_t)p0; p < p1; ++p) {
-        while (p >= next) next = rowptr[++row + 1];
-        const int32_t prev = p == rowptr[row] ? row : col[p - 1];
-        const int32_t c = col[p];
-        bad |= (c <= prev) | (c >= n);
-        src_out[p] = row;
+    if (tally) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) work += __shfl_xor(work, o);
+        if (__lane_id() == 0 && work) atomicAdd(&ctl->merge_work, work);
     }
-    if (bad) atomicOr(&ctl->err, 16);
 }
 
 __global__ __launch_bounds__(kBlock) void k_init_eid_s(int32_t* __restrict__ eid, int32_t* __restrict__ S, int32_t m) {
@@ -122,12 +135,12 @@ __global__ __launch_bounds__(kBlock) void k_prune_canonical(const int32_t* __res
 }  // namespace
 
 hipError_t launch_validate(const int32_t* rowptr, const int32_t* col, int32_t n, int32_t m, int32_t* src_out,
-                           Ctl* ctl, hipStream_t s) {
+                           Ctl* ctl, bool tally, hipStream_t s) {
     k_ctl_reset<<<1, 64, 0, s>>>(ctl, m);
     k_validate_rowptr<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(rowptr, n, m, ctl);
     if (n > 0 && m > 0)
         k_validate_rows<<<grid_for(((int64_t)m + kValSpan - 1) / kValSpan), kBlock, 0, s>>>(rowptr, col, n, m, src_out,
-                                                                                           ctl);
+                                                                                           ctl, tally);
     return hipGetLastError();
 }
 

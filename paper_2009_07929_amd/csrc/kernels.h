@@ -8,7 +8,7 @@ namespace kt {
 
 // ---- input validation and set-up (k_setup.hip)
 hipError_t launch_validate(const int32_t* rowptr, const int32_t* col, int32_t n, int32_t m, int32_t* src_out,
-                           Ctl* ctl, hipStream_t s);
+                           Ctl* ctl, bool tally, hipStream_t s);
 hipError_t launch_init_run(const Buf& b, const int32_t* rowptr, const int32_t* col, int32_t n, int32_t m,
                            hipStream_t s);
 hipError_t launch_set_final(Ctl* ctl, int f, hipStream_t s);

@@ -20,6 +20,9 @@ def test_to_tuning_fields():
     t = autotune.to_tuning(cfg)
     assert t.hub_chunk_tasks == 64 and t.rounds_per_sync == 4 and abs(t.learned_hub_min - 12.5) < 1e-6
     assert t.wave_min_work == cfg["wave_min_work"] and t.hub_min_work == cfg["hub_min_work"]
+    assert autotune.to_tuning(dict(cfg, plain_max_work=128)).plain_max_work == 128
+    old = {k: v for k, v in cfg.items() if k != "plain_max_work"}   # entries cached before the gate existed
+    assert autotune.to_tuning(old).plain_max_work == 0
 
 
 def test_cache_roundtrip(tmp_path):

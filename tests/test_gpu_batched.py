@@ -84,6 +84,7 @@ def test_graph_replay_equals_host_loop(rps, schedule, rmat12):
     g = kt().Graph(rp, col, device="cuda", schedule=schedule)
     t = kt().ktruss_tuning()
     t.rounds_per_sync = rps
+    t.plain_max_work = -1
     kt().ktruss_set_schedule(g, schedule, None, t)
     for K in (3, 5, 8, 30):
         print("case graph-replay rps=%d schedule=%d K=%d" % (rps, schedule, K), flush=True)

@@ -1,0 +1,76 @@
+"""The light-graph gate of the heuristic and learned schedules: the run goes
+thread-per-edge exactly when the input's summed merge length (row tail after
+each edge plus the length of row kappa) is at most plain_max_work x m, and the
+results equal the oracle's either way."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from conftest import gpu_available
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
+
+
+def kt():
+    from paper_2009_07929_amd import ktruss
+    return ktruss
+
+
+def merge_work(rp, col):
+    """Sum over edges e = (i, kappa) of |row i after e| + |row kappa|, from the CSR alone."""
+    rp = np.asarray(rp, np.int64)
+    d = np.diff(rp)
+    rows = np.repeat(np.arange(len(d)), d)
+    tail = rp[rows + 1] - np.arange(len(col)) - 1
+    return int(tail.sum() + d[np.asarray(col, np.int64)].sum())
+
+
+def run_counted(rp, col, K, schedule, plain_max_work, params=None):
+    import torch
+    g = kt().Graph(rp, col, device="cuda")
+    t = kt().ktruss_tuning()
+    t.plain_max_work = plain_max_work
+    t.hub_min_work = 1      # heuristic: every row with an in-edge is a hub row unless the gate is taken
+    kt().ktruss_set_schedule(g, schedule, params, t)
+    kt().ktruss_profile_enable(True)
+    try:
+        mask, sup, rounds = kt().ktruss_run(g, K)
+        torch.cuda.synchronize()
+        hub = kt().ktruss_profile_read(kt().PROFILE_HUB)[0]
+        thread = kt().ktruss_profile_read(kt().PROFILE_THREAD)[0]
+    finally:
+        kt().ktruss_profile_enable(False)
+    return mask.cpu().numpy(), sup.cpu().numpy(), rounds, hub, thread
+
+
+@pytest.mark.parametrize("schedule", [1, 2])
+@pytest.mark.parametrize("name", ["ba", "rmat13"])
+def test_gate_threshold_is_exact(name, schedule):
+    if name == "ba":
+        n, s, d = synth.barabasi_albert(3000, 6, 5)
+    else:
+        n, s, d = synth.rmat(13, 16, 0.57, 0.19, 0.19, 9)
+    rp, col, _ = kt().ktruss_build_csr(s, d, n)
+    m = len(col)
+    W = merge_work(rp, col)
+    lo = W // m            # W > lo * m unless m divides W: the gate stays shut
+    params = None
+    if schedule == 2:
+        import torch
+        theta = np.zeros(kt().MLP_PARAMS, np.float32)
+        theta[-1] = 40.0
+        params = torch.from_numpy(theta).cuda()
+    K = 4
+    om, osup, orounds = oracle.truss(rp, col, K, "P")
+    cases = [(lo + 1, True), (-1, False)]
+    if W % m:
+        cases.append((lo, False))
+    for thr, gated in cases:
+        print("case gate %s schedule=%d W=%d m=%d thr=%d" % (name, schedule, W, m, thr), flush=True)
+        gm, gs, gr, hub, thread = run_counted(rp, col, K, schedule, thr, params)
+        assert np.array_equal(gm, om) and np.array_equal(gs, osup) and gr == orounds
+        if gated:
+            assert hub == 0 and thread == gr, (hub, thread, gr)
+        else:
+            assert hub > 0, (hub, thread)

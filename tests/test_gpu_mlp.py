@@ -76,6 +76,9 @@ def test_adam_matches_reference():
 def learned_run(rp, col, K, params, tuning=None):
     import torch
     g = kt().Graph(rp, col, device="cuda")
+    if tuning is None:
+        tuning = kt().ktruss_tuning()
+    tuning.plain_max_work = -1   # exercise the learned bins even on light graphs
     kt().ktruss_set_schedule(g, kt().SCHED_LEARNED, params, tuning)
     mask, sup, rounds = kt().ktruss_run(g, K)
     torch.cuda.synchronize()

@@ -25,7 +25,9 @@ def run_gpu(rp, col, K, schedule=0):
     import torch
     g = kt().Graph(rp, col, device="cuda")
     if schedule:
-        kt().ktruss_set_schedule(g, schedule)
+        t = kt().ktruss_tuning()
+        t.plain_max_work = -1   # exercise the schedule even on light graphs
+        kt().ktruss_set_schedule(g, schedule, None, t)
     mask, sup, rounds = kt().ktruss_run(g, K)
     torch.cuda.synchronize()
     return mask.cpu().numpy(), sup.cpu().numpy(), rounds
