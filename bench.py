@@ -44,15 +44,16 @@ def recorded_traffic(workload, schedule):
     """Per-launch HBM bytes of the support kernel from the rocprofv3 counter runs
     recorded in profiles/traffic.json (FETCH_SIZE and WRITE_SIZE, scaled by the
     copy-kernel calibration); None if none was recorded for this workload and
-    schedule, or if the kernel source changed since."""
+    schedule, or if the kernel's sources (its file and the shared header)
+    changed since."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path)).get("%s/%s" % (workload, schedule))
     if not rec:
         return None
-    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+    src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in rec["sources"])
+    if hashlib.sha256(src).hexdigest() != rec["sources_sha256"]:
         return None
     return (rec["fetch_kib_avg"] * rec["fetch_scale"] + rec["write_kib_avg"] * rec["write_scale"]) * 1024.0
 

@@ -67,7 +67,8 @@ typedef struct ktruss_tuning {
     float learned_hub_min;   /* learned: rows whose predicted log2 cycles reach this are hub rows (0: 12) */
     int32_t hub_chunk_tasks; /* heuristic/force-hub: tasks per hub item (clamped to 16..256) */
     int32_t plain_max_work;  /* heuristic/learned: if the input's mean merge length per edge (row tail + row
-                                kappa) is at most this, ktruss_run/ktruss_support use thread-per-edge for
+                                kappa; the row-kappa lengths sampled on edges 0, 16, 32, ... and weighted
+                                by 16) is at most this, ktruss_run/ktruss_support use thread-per-edge for
                                 every task and build no in-edge lists; 0: default 32, negative: never */
     int32_t reserved[1];
 } ktruss_tuning;

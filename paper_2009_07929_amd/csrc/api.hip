@@ -65,6 +65,7 @@ FullLayout full_layout(int32_t n, int64_t m, int32_t G) {
     }
     L.cedge = take(em);
     L.csrc = take(em);
+    L.ckey = take(em);
     L.cptr = take(vn);
     L.xscan = take(em1);
     L.cxscan = take(em1);
@@ -121,6 +122,7 @@ Work carve(void* work, int32_t n, int64_t m, int32_t G) {
         w.b[b].rowptr = (int32_t*)(base + L.rowptr[b]);
         w.c[b].edge = (int32_t*)(base + L.cedge);  // one set of in-edge lists, remapped in place
         w.c[b].src = (int32_t*)(base + L.csrc);
+        w.c[b].key = (int32_t*)(base + L.ckey);
         w.c[b].ptr = (int32_t*)(base + L.cptr);
     }
     w.sc.xscan = (int32_t*)(base + L.xscan);
@@ -196,7 +198,8 @@ int32_t check_graph(const ktruss_graph* g, bool need_work) {
 
 // Validates the input CSR on the device (writing each edge's row into
 // src_out) and reads the verdict back.  Synchronises s.  merge_work: if not
-// null, receives the input's merge length summed over its edges.
+// null, receives the light-graph gate's statistic (the input's merge length
+// summed over its edges, the row-kappa part sampled).
 int32_t validate_on_device(const int32_t* rowptr, const int32_t* col, int32_t n, int32_t m, const Work& w,
                            int32_t* src_out, hipStream_t s, unsigned long long* merge_work = nullptr) {
     HIP_TRY(launch_validate(rowptr, col, n, m, src_out, w.ctl, merge_work != nullptr, s), "validate launch");
@@ -307,9 +310,10 @@ unsigned long long* profile_work() {
 bool uses_csc(int sched) { return sched != KTRUSS_SCHED_PLAIN && sched != KTRUSS_SCHED_FORCE_WAVE; }
 
 // Light-graph gate of the heuristic and learned schedules: an input whose
-// mean merge length per edge is at most plain_max_work (0: the default,
-// negative: never) has no task long enough to pay for in-edge lists, staging
-// or binning, so the run is thread-per-edge throughout.
+// mean merge length per edge (row tails exact, row-kappa lengths sampled on
+// every 16th edge) is at most plain_max_work (0: the default, negative:
+// never) has no task long enough to pay for in-edge lists, staging or
+// binning, so the run is thread-per-edge throughout.
 bool gated(const ktruss_graph* g) {
     return (g->schedule == KTRUSS_SCHED_HEURISTIC || g->schedule == KTRUSS_SCHED_LEARNED) &&
            g->tuning.plain_max_work >= 0;

@@ -69,13 +69,14 @@ struct Buf {
 };
 
 // In-edge lists: for every row kappa, the positions of the edges whose column
-// is kappa (edge[ptr[kappa] .. ptr[kappa+1])) and their rows.  Built once per
-// run; after every prune the positions are remapped in place and the entries
-// of removed edges become tombstones (edge = -1), so the lists keep their
-// length (Ctl::csc_m) for the whole run.
+// is kappa (edge[ptr[kappa] .. ptr[kappa+1])), their rows (src) and kappa
+// itself (key).  Built once per run; after every prune the positions are
+// remapped in place and the entries of removed edges become tombstones
+// (edge = -1), so the lists keep their length (Ctl::csc_m) for the whole run.
 struct Csc {
     int32_t* edge;
     int32_t* src;
+    int32_t* key;
     int32_t* ptr;
 };
 
@@ -134,7 +135,7 @@ __host__ __device__ inline int64_t hit_word_index(int32_t e, int32_t c, int64_t 
 
 struct Layout {
     size_t col[2], src[2], eid[2], S[2], rowptr[2];
-    size_t cedge, csrc, cptr;
+    size_t cedge, csrc, ckey, cptr;
     size_t xscan, cxscan, blockcnt, blockoff, blockcnt2, blockoff2, alive_in, itemoff, items, ctail,
         is_hub, hub_row, hitw, wave_tasks, thread_tasks, insum, cycles, act_off, act_list, feats, pred, chunk_sz,
         rs_hist;

@@ -301,7 +301,7 @@ __global__ __launch_bounds__(kBlock) void k_in_outdeg_sum(Buf x, Csc c, int32_t 
     long long v = 0;
     if (i < m) {
         const int32_t r = c.src[i];
-        key = x.col[c.edge[i]];
+        key = c.key[i];
         v = x.rowptr[r + 1] - x.rowptr[r];
     }
 #pragma unroll
@@ -420,10 +420,10 @@ struct TaskClass {
     const uint8_t* is_hub;
     int32_t wave_min;
     __device__ int cls(int32_t i) const {
+        const int32_t k = c.key[i];
+        if (is_hub[k]) return 0;
         const int32_t e = c.edge[i];
         if (e < 0) return 0;  // tombstone of a removed edge
-        const int32_t k = x.col[e];
-        if (is_hub[k]) return 0;
         const int32_t tail = x.rowptr[c.src[i] + 1] - e - 1;
         const int32_t d = x.rowptr[k + 1] - x.rowptr[k];
         if (tail == 0 || d == 0) return 0;  // no triangle can close on this task
@@ -526,7 +526,7 @@ hipError_t launch_build_csc(const Buf& b, const Csc& c, int32_t n, int32_t m, Sc
     const int32_t* vin = nullptr;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
-        int32_t* kout = kbuf[p & 1];
+        int32_t* kout = p == passes - 1 ? c.key : kbuf[p & 1];
         int32_t* vout = p == passes - 1 ? c.edge : vbuf[p & 1];
         k_rs_hist<<<nblk, kBlock, 0, s>>>(kin, m, shift, nblk, sc.rs_hist);
         device_scan(FromArray{sc.rs_hist}, nh, nullptr, sc, sc.rs_hist, nullptr, s);

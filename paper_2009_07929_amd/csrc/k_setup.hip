@@ -49,9 +49,10 @@ __global__ __launch_bounds__(kBlock) void k_validate_rowptr(const int32_t* __res
 // checked monotone) and walks on, so long rows cost no more than short ones.
 constexpr int kValSpan = 16;
 
-// tally: also sums every edge's merge length (the tail of its row after it
-// plus the length of row kappa = its column) into ctl->merge_work, the input
-// statistic of the light-graph gate.
+// tally: also accumulates the input statistic of the light-graph gate into
+// ctl->merge_work: the tail of every edge's row after it, exactly, plus the
+// length of row kappa (the edge's column) sampled on the first edge of every
+// span of kValSpan edges and weighted by the span's edge count.
 __global__ __launch_bounds__(kBlock) void k_validate_rows(const int32_t* __restrict__ rowptr,
                                                         const int32_t* __restrict__ col, int32_t n, int32_t m,
                                                         int32_t* __restrict__ src_out, Ctl* ctl, bool tally) {
@@ -76,7 +77,10 @@ __global__ __launch_bounds__(kBlock) void k_validate_rows(const int32_t* __restr
             const bool b = (c <= prev) | (c >= n);
             bad |= b;
             src_out[p] = row;
-            if (tally && !b) work += (unsigned long long)(next - p - 1 + rowptr[c + 1] - rowptr[c]);
+            if (tally && !b) {
+                work += (unsigned long long)(next - p - 1);
+                if (p == p0) work += (unsigned long long)(p1 - p0) * (unsigned long long)(rowptr[c + 1] - rowptr[c]);
+            }
         }
         if (bad) atomicOr(&ctl->err, 16);
     }

@@ -1,7 +1,8 @@
 """The light-graph gate of the heuristic and learned schedules: the run goes
 thread-per-edge exactly when the input's summed merge length (row tail after
-each edge plus the length of row kappa) is at most plain_max_work x m, and the
-results equal the oracle's either way."""
+each edge, plus the length of row kappa sampled on edges 0, 16, 32, ... with
+weight 16, the last span weighted by its edge count) is at most
+plain_max_work x m, and the results equal the oracle's either way."""
 import numpy as np
 import pytest
 
@@ -17,13 +18,17 @@ def kt():
     return ktruss
 
 
-def merge_work(rp, col):
-    """Sum over edges e = (i, kappa) of |row i after e| + |row kappa|, from the CSR alone."""
+def merge_work(rp, col, span=16):
+    """Sum over edges e = (i, kappa) of |row i after e|, plus |row kappa| of
+    every span-th edge times the number of edges in its span."""
     rp = np.asarray(rp, np.int64)
     d = np.diff(rp)
+    m = len(col)
     rows = np.repeat(np.arange(len(d)), d)
-    tail = rp[rows + 1] - np.arange(len(col)) - 1
-    return int(tail.sum() + d[np.asarray(col, np.int64)].sum())
+    tail = rp[rows + 1] - np.arange(m) - 1
+    first = np.arange(0, m, span)
+    weight = np.minimum(span, m - first)
+    return int(tail.sum() + (weight * d[np.asarray(col, np.int64)[first]]).sum())
 
 
 def run_counted(rp, col, K, schedule, plain_max_work, params=None):
