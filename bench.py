@@ -7,7 +7,8 @@ resident in HBM.  value = edges processed per second = (number of K values x m)
 / step time: the paper's ME/s definition (input edges over the wall time of a
 complete K-truss), summed over the sweep.
 
-Extra legs (on by default, --no-extras to skip), reported inside the same line:
+Extra legs (on by default; --extras picks some, --no-extras skips all), reported
+inside the same line:
   batched: 4096 Chung-Lu graphs (K per graph) in one batched run with the
            autotuner's cached schedule and tiles, edges/s = sum of edges /
            batch time, next to the same graphs run one at a time with the plain
@@ -109,7 +110,13 @@ def single_sweep(args, kt, torch):
     log("workload %s: n=%d m=%d (gen %.1fs, csr %.1fs)" % (args.workload, n, m, t_gen, t_build))
 
     g = kt.Graph(rowptr, col, device="cuda:0")
-    kt.ktruss_set_schedule(g, SCHEDULES[args.schedule], None, tuning(kt, args.rounds_per_sync))
+    params = None
+    if args.schedule == "learned":
+        from paper_2009_07929_amd import cost_model
+        params = cost_model.load_params("cuda:0")
+        if params is None:
+            raise RuntimeError("--schedule learned needs the trained cost-model weights")
+    kt.ktruss_set_schedule(g, SCHEDULES[args.schedule], params, tuning(kt, args.rounds_per_sync))
     mask = torch.empty(m, dtype=torch.uint8, device="cuda:0")
     sup = torch.empty(m, dtype=torch.int32, device="cuda:0")
     stream = torch.cuda.current_stream()
@@ -132,7 +139,7 @@ def single_sweep(args, kt, torch):
         per_k[str(K)] = {"rounds": r, "ms": dt * 1e3, "edges_per_s": m / dt, "truss_edges": int(mask.sum().item())}
     # support-pass timing: HIP events on the launch stream, host-loop rounds
     # (graph-replayed rounds are not bracketed by events)
-    kt.ktruss_set_schedule(g, SCHEDULES[args.schedule], None, tuning(kt, 0))
+    kt.ktruss_set_schedule(g, SCHEDULES[args.schedule], params, tuning(kt, 0))
     kt.ktruss_profile_enable(True)
     for K in Ks:
         kt.ktruss_run(g, K, mask, sup, stream)
@@ -145,7 +152,7 @@ def single_sweep(args, kt, torch):
         if nl:
             kinds[name] = {"launches": nl, "ms": ms, "tasks": tasks}
     kt.ktruss_profile_enable(False)
-    kt.ktruss_set_schedule(g, SCHEDULES[args.schedule], None, tuning(kt, args.rounds_per_sync))
+    kt.ktruss_set_schedule(g, SCHEDULES[args.schedule], params, tuning(kt, args.rounds_per_sync))
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -330,6 +337,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--extras", default="batched,learned",
+                    help="comma-separated extra legs to run after the main leg (batched, learned)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched leg: ignore the autotuner's cached configuration")
     ap.add_argument("--batch-graphs", type=int, default=4096)
@@ -359,9 +368,14 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    if not args.no_extras:
+    extras = set() if args.no_extras else {e for e in args.extras.split(",") if e}
+    unknown = extras - {"batched", "learned"}
+    if unknown:
+        raise SystemExit("unknown extra legs: %s" % ",".join(sorted(unknown)))
+    if "batched" in extras:
         log("batched leg ...")
         out["batched"] = batched_leg(args, kt, torch, args.batch_graphs)
+    if "learned" in extras:
         log("learned-schedule leg ...")
         out["learned"] = learned_leg(args, kt, torch)
     out["cpu_baseline"] = None

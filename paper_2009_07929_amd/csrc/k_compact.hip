@@ -31,11 +31,9 @@ struct CsrRound {
     Buf x, y;
     int32_t thr;
     BatchCtx b;
-    int32_t* alive_in;  // alive in-edges per row (in-edge lists kept), or null
     __device__ int32_t load(int32_t e) const { return e; }
     __device__ bool keep(int32_t e) const { return round_keep(x, b, thr, e); }
     __device__ void drop(int32_t e, int32_t) const {
-        if (alive_in) atomicSub(&alive_in[x.col[e]], 1);
         if (b.thrv && b.done_now[b.gidv[x.src[e]]]) {
             const int32_t c = x.eid[e];
             b.mask[c] = 1;
@@ -54,12 +52,9 @@ struct CsrRound {
 struct CsrAlive {
     Buf x, y;
     const uint8_t* alive_can;
-    int32_t* alive_in;  // alive in-edges per row (in-edge lists kept), or null
     __device__ int32_t load(int32_t e) const { return e; }
     __device__ bool keep(int32_t e) const { return alive_can[x.eid[e]] != 0; }
-    __device__ void drop(int32_t e, int32_t) const {
-        if (alive_in) atomicSub(&alive_in[x.col[e]], 1);
-    }
+    __device__ void drop(int32_t, int32_t) const {}
     __device__ void emit(int32_t e, int32_t, int32_t q) const {
         y.col[q] = x.col[e];
         y.src[q] = x.src[e];
@@ -177,19 +172,47 @@ __global__ __launch_bounds__(kBlock) void k_ptr_remap(const int32_t* __restrict_
     new_ptr[s] = v < 0 ? ~v : v;
 }
 
+__global__ __launch_bounds__(kBlock) void k_zero_rows(int32_t* __restrict__ a, int32_t n, const Ctl* __restrict__ ctl,
+                                                    int round) {
+    if (round && ctl->done) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) a[i] = 0;
+}
+
 // In-edge lists after the CSR filter, in place: every entry's edge position
 // becomes the edge's new position (xscan holds q for a kept edge, ~q for a
-// removed one); entries of removed edges, and tombstones, stay -1.
-__global__ __launch_bounds__(kBlock) void k_csc_remap(int32_t* __restrict__ cedge, const int32_t* __restrict__ xscan,
+// removed one); entries of removed edges, and tombstones, stay -1.  The alive
+// entries of every row kappa are counted on the way (alive_in, zeroed
+// before): the lists are grouped by kappa (key), so a wave-level segmented
+// sum adds each run and its last lane issues one atomic per run piece.
+__global__ __launch_bounds__(kBlock) void k_csc_remap(int32_t* __restrict__ cedge, const int32_t* __restrict__ ckey,
+                                                    const int32_t* __restrict__ xscan, int32_t* __restrict__ alive_in,
                                                     const Ctl* __restrict__ ctl, int round) {
     if (round && ctl->done) return;
     const int32_t N = ctl->csc_m;
-    for (int32_t c = (int32_t)(blockIdx.x * kBlock + threadIdx.x); c < N; c += (int32_t)(gridDim.x * kBlock)) {
-        const int32_t e = cedge[c];
-        if (e >= 0) {
-            const int32_t v = xscan[e];
-            cedge[c] = v >= 0 ? v : -1;
+    const int lane = __lane_id();
+    const int32_t stride = (int32_t)(gridDim.x * kBlock);
+    // wave-uniform loop: lanes take 64 consecutive entries
+    for (int32_t c0 = (int32_t)(blockIdx.x * kBlock + (threadIdx.x & ~63u)); c0 < N; c0 += stride) {
+        const int32_t c = c0 + lane;
+        int32_t key = -1, v = 0;
+        if (c < N) {
+            const int32_t e = cedge[c];
+            if (e >= 0) {
+                const int32_t q = xscan[e];
+                cedge[c] = q >= 0 ? q : -1;
+                v = q >= 0;
+            }
+            key = ckey[c];
         }
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t u = __shfl_up(v, o);
+            const int32_t kk = __shfl_up(key, o);
+            if (lane >= o && kk == key) v += u;
+        }
+        const int32_t next = __shfl_down(key, 1);
+        if (c < N && v && (lane == 63 || next != key)) atomicAdd(&alive_in[key], v);
     }
 }
 
@@ -224,17 +247,17 @@ hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* 
                           int32_t csc_hint, hipStream_t s) {
     const int round = mode == 0;
     const bool batch = b.thrv != nullptr;
-    int32_t* alive_in = cx ? sc.alive_in : nullptr;
     if (mode == 0) {
-        run_filter(CsrRound{x, y, thr, b, alive_in}, ctl, p, batch ? 3 : 1, 1, sc.blockcnt, sc.blockoff, sc.xscan,
-                   m_hint, s);
+        run_filter(CsrRound{x, y, thr, b}, ctl, p, batch ? 3 : 1, 1, sc.blockcnt, sc.blockoff, sc.xscan, m_hint, s);
     } else {
-        run_filter(CsrAlive{x, y, alive_can, alive_in}, ctl, p, 2, 0, sc.blockcnt, sc.blockoff, sc.xscan, m_hint, s);
+        run_filter(CsrAlive{x, y, alive_can}, ctl, p, 2, 0, sc.blockcnt, sc.blockoff, sc.xscan, m_hint, s);
     }
     k_ptr_remap<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(x.rowptr, y.rowptr, n, sc.xscan, ctl, round);
-    if (cx && csc_hint > 0)  // the in-edge lists (remapped in place; cy is the same set)
-        k_csc_remap<<<min(grid_for(csc_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(cx->edge, sc.xscan, ctl,
-                                                                                         round);
+    if (cx && csc_hint > 0) {  // the in-edge lists (remapped in place; cy is the same set) and alive in-edge counts
+        k_zero_rows<<<grid_for(n), kBlock, 0, s>>>(sc.alive_in, n, ctl, round);
+        k_csc_remap<<<min(grid_for(csc_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(cx->edge, cx->key, sc.xscan,
+                                                                                         sc.alive_in, ctl, round);
+    }
     (void)cy;
     if (batch && mode == 0) k_batch_end<<<1, 64, 0, s>>>(ctl, p);
     return hipGetLastError();

@@ -246,7 +246,8 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
         }
         // block end: lane j writes chunk j's hit word and adds its hits to S(i, kappa)
         const unsigned long long word = ((unsigned long long)word_hi << 32) | word_lo;
-        if (dv && dc < kHitWords) hitw[hit_word_index(de, dc, hit_stride)] = word;
+        // written once and read once by k_hit_sum: a streaming store keeps L2 for the tails
+        if (dv && dc < kHitWords) __builtin_nontemporal_store(word, &hitw[hit_word_index(de, dc, hit_stride)]);
         const int32_t cnt = __popcll(word);
         if (dv && cnt) atomicAdd(&x.S[de], cnt);
     }
