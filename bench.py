@@ -251,6 +251,8 @@ def batched_leg(args, kt, torch, count):
            "max_rounds": int(batch_rounds.max()),
            "schedule": cfg["schedule"] if cfg else args.schedule, "autotuned": cfg}
     del b, mask, sup
+    if args.no_per_graph:
+        return out
     # the same graphs one at a time (graph and output buffers resident before timing)
     for name in ("plain", args.schedule):
         graphs = [kt.Graph(rp, c, device="cuda:0", schedule=SCHEDULES[name]) for rp, c in csr]
@@ -342,6 +344,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched leg: ignore the autotuner's cached configuration")
     ap.add_argument("--batch-graphs", type=int, default=4096)
+    ap.add_argument("--no-per-graph", action="store_true",
+                    help="batched leg without the one-graph-at-a-time baselines (for profiling the batched run)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after the timed region, copy a device buffer of this size 3 times (a plain copy "
                          "kernel of known traffic, for scaling hardware byte counters)")

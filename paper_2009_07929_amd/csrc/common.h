@@ -53,6 +53,8 @@ struct Ctl {
     int32_t n_active;    // rows with support work in the current pass (learned schedule, sampling)
     int32_t n_samples;   // cost-model samples written so far
     int32_t csc_m;       // in-edge list entries (alive edges + tombstones of removed ones)
+    int32_t csc_pack;    // the lists are being packed in this round (tombstones dominate)
+    int32_t csc_next;    // entries after packing
     int64_t removed_total;
     unsigned long long merge_work;  // input's merge length summed over its edges (row tail + row kappa)
 };

@@ -85,16 +85,10 @@ __global__ __launch_bounds__(kBlock) void k_filter_count(P pol, const Ctl* __res
     if (threadIdx.x == 0) blockcnt[blockIdx.x] = c;
 }
 
-// update: 0 = only the scan; 1 = prune-round bookkeeping (pass count,
-// fixpoint flag, survivor count); 2 = set the survivor count of buffer 1-p;
-// 3 = batched prune round (pass count, survivor count; the run ends in
-// k_batch_end once nothing is kept).
-__global__ __launch_bounds__(kScanThreads) void k_filter_scan(const int32_t* __restrict__ blockcnt,
-                                                            int32_t* __restrict__ blockoff, int32_t G, Ctl* ctl,
-                                                            int p, int update, int round,
-                                                            int32_t* __restrict__ xscan) {
-    __shared__ int s_wave[kScanThreads / 64];
-    if (round && ctl->done) return;
+// Exclusive scan of the G per-workgroup counts into blockoff (one workgroup
+// of kScanThreads); returns the total.
+__device__ __forceinline__ int scan_block_counts(const int32_t* __restrict__ blockcnt, int32_t* __restrict__ blockoff,
+                                                 int32_t G, int* s_wave) {
     constexpr int PER = kMaxScanBlocks / kScanThreads;
     const int t = threadIdx.x;
     int v[PER];
@@ -113,6 +107,21 @@ __global__ __launch_bounds__(kScanThreads) void k_filter_scan(const int32_t* __r
         if (idx < G) blockoff[idx] = run;
         run += v[j];
     }
+    return total;
+}
+
+// update: 0 = only the scan; 1 = prune-round bookkeeping (pass count,
+// fixpoint flag, survivor count); 2 = set the survivor count of buffer 1-p;
+// 3 = batched prune round (pass count, survivor count; the run ends in
+// k_batch_end once nothing is kept).
+__global__ __launch_bounds__(kScanThreads) void k_filter_scan(const int32_t* __restrict__ blockcnt,
+                                                            int32_t* __restrict__ blockoff, int32_t G, Ctl* ctl,
+                                                            int p, int update, int round,
+                                                            int32_t* __restrict__ xscan) {
+    __shared__ int s_wave[kScanThreads / 64];
+    if (round && ctl->done) return;
+    const int t = threadIdx.x;
+    const int total = scan_block_counts(blockcnt, blockoff, G, s_wave);
     if (t == 0) {
         const int32_t N = ctl->m_buf[p];
         xscan[N] = total;
@@ -216,6 +225,99 @@ __global__ __launch_bounds__(kBlock) void k_csc_remap(int32_t* __restrict__ cedg
     }
 }
 
+// ---- packing of the in-edge lists.  Tombstones keep every per-entry kernel
+// at the run's edge count; once they outnumber the alive entries
+// (kCscPackRatio), the lists are compacted in order (count, scan, scatter
+// into scratch, row pointers remapped, copied back), so that later passes
+// cost the alive count.  Decided on the device: replayed rounds pack too.
+constexpr int kCscPackRatio = 2;
+
+__global__ void k_csc_pack_decide(Ctl* ctl, int p, int round) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int32_t alive = ctl->m_buf[1 - p];
+    ctl->csc_pack = !(round && ctl->done) && alive > 0 && (int64_t)ctl->csc_m > (int64_t)kCscPackRatio * alive;
+}
+
+__global__ __launch_bounds__(kBlock) void k_csc_pack_count(Csc c, const Ctl* __restrict__ ctl,
+                                                         int32_t* __restrict__ blockcnt) {
+    __shared__ int s_wave[kBlock / 64];
+    if (!ctl->csc_pack) return;
+    int32_t lo, hi;
+    chunk_of(ctl->csc_m, lo, hi);
+    int k = 0;
+    for (int32_t i = lo + (int32_t)threadIdx.x; i < hi; i += kBlock) k += c.edge[i] >= 0;
+    k = block_sum<kBlock>(k, s_wave);
+    if (threadIdx.x == 0) blockcnt[blockIdx.x] = k;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_csc_pack_scan(const int32_t* __restrict__ blockcnt,
+                                                              int32_t* __restrict__ blockoff, int32_t G, Ctl* ctl,
+                                                              int32_t* __restrict__ cscan) {
+    __shared__ int s_wave[kScanThreads / 64];
+    if (!ctl->csc_pack) return;
+    const int total = scan_block_counts(blockcnt, blockoff, G, s_wave);
+    if (threadIdx.x == 0) {
+        cscan[ctl->csc_m] = total;
+        ctl->csc_next = total;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_csc_pack_scatter(Csc c, Csc t, const Ctl* __restrict__ ctl,
+                                                           const int32_t* __restrict__ blockoff,
+                                                           int32_t* __restrict__ cscan) {
+    __shared__ int s_wave[kBlock / 64];
+    if (!ctl->csc_pack) return;
+    int32_t lo, hi;
+    chunk_of(ctl->csc_m, lo, hi);
+    int32_t base = blockoff[blockIdx.x];
+    for (int32_t t0 = lo; t0 < hi; t0 += kBlock) {
+        const int32_t i = t0 + (int32_t)threadIdx.x;
+        const bool in = i < hi;
+        const int32_t e = in ? c.edge[i] : -1;
+        const bool k = e >= 0;
+        int tot;
+        const int32_t q = base + block_excl_flag<kBlock>(k, s_wave, tot);
+        if (in) {
+            cscan[i] = k ? q : ~q;
+            if (k) {
+                t.edge[q] = e;
+                t.src[q] = c.src[i];
+                t.key[q] = c.key[i];
+            }
+        }
+        base += tot;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_csc_pack_ptr(const int32_t* __restrict__ old_ptr,
+                                                       int32_t* __restrict__ new_ptr, int32_t n,
+                                                       const int32_t* __restrict__ cscan, const Ctl* __restrict__ ctl) {
+    if (!ctl->csc_pack) return;
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s > n) return;
+    const int32_t v = cscan[old_ptr[s]];
+    new_ptr[s] = v < 0 ? ~v : v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_csc_pack_copy(Csc c, Csc t, int32_t n, const Ctl* __restrict__ ctl) {
+    if (!ctl->csc_pack) return;
+    const int32_t N = ctl->csc_next;
+    const int32_t stride = (int32_t)(gridDim.x * kBlock);
+    for (int32_t i = (int32_t)(blockIdx.x * kBlock + threadIdx.x); i < N; i += stride) {
+        c.edge[i] = t.edge[i];
+        c.src[i] = t.src[i];
+        c.key[i] = t.key[i];
+    }
+    for (int32_t i = (int32_t)(blockIdx.x * kBlock + threadIdx.x); i <= n; i += stride) c.ptr[i] = t.ptr[i];
+}
+
+__global__ void k_csc_pack_end(Ctl* ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && ctl->csc_pack) {
+        ctl->csc_m = ctl->csc_next;
+        ctl->csc_pack = 0;
+    }
+}
+
 // Batched form: the run ends after the pass that leaves no edge.
 __global__ void k_batch_end(Ctl* ctl, int p) {
     if (threadIdx.x == 0 && !ctl->done && ctl->m_buf[1 - p] == 0) {
@@ -257,6 +359,16 @@ hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* 
         k_zero_rows<<<grid_for(n), kBlock, 0, s>>>(sc.alive_in, n, ctl, round);
         k_csc_remap<<<min(grid_for(csc_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(cx->edge, cx->key, sc.xscan,
                                                                                          sc.alive_in, ctl, round);
+        // packing when tombstones dominate; scratch that the next preparation rebuilds holds the packed copy
+        const Csc t{sc.wave_tasks, sc.thread_tasks, sc.ctail, sc.itemoff};
+        const int32_t G = filter_grid(csc_hint);
+        k_csc_pack_decide<<<1, 64, 0, s>>>(ctl, p, round);
+        k_csc_pack_count<<<G, kBlock, 0, s>>>(*cx, ctl, sc.blockcnt);
+        k_csc_pack_scan<<<1, kScanThreads, 0, s>>>(sc.blockcnt, sc.blockoff, G, ctl, sc.cxscan);
+        k_csc_pack_scatter<<<G, kBlock, 0, s>>>(*cx, t, ctl, sc.blockoff, sc.cxscan);
+        k_csc_pack_ptr<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(cx->ptr, t.ptr, n, sc.cxscan, ctl);
+        k_csc_pack_copy<<<min(grid_for(csc_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(*cx, t, n, ctl);
+        k_csc_pack_end<<<1, 64, 0, s>>>(ctl);
     }
     (void)cy;
     if (batch && mode == 0) k_batch_end<<<1, 64, 0, s>>>(ctl, p);

@@ -22,6 +22,8 @@ __global__ void k_ctl_reset(Ctl* ctl, int32_t m) {
         ctl->n_active = 0;
         ctl->n_samples = 0;
         ctl->csc_m = m;
+        ctl->csc_pack = 0;
+        ctl->csc_next = m;
         ctl->merge_work = 0ull;
         ctl->removed_total = 0;
     }
