@@ -119,6 +119,7 @@ __device__ __forceinline__ void wave_task(const Buf& x, int32_t e) {
 // them to S(i, w) row by row after the pass.
 enum { kModeBitmap = 0, kModeKeys = 1, kModeGlobal = 2 };
 static_assert(kHubChunk <= kHubThreads, "each wave holds at most 64 of an item's tasks in registers");
+static_assert(64 % kHubUnroll == 0, "a step's chunk indices jj + u stay within the 64 lanes");
 
 // The task loop of one hub item, for one wave.  The wave's tasks (kk = wave,
 // wave + 4, ...; at most 64, lane r holds task r) are cut into 64-element
@@ -174,15 +175,15 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
             int32_t ub[kHubUnroll], ul[kHubUnroll], uw[kHubUnroll];
 #pragma unroll
             for (int u = 0; u < kHubUnroll; ++u) {
-                const int32_t q = min(jj + u, 63);
-                ub[u] = __builtin_amdgcn_readlane(dbase, q);
-                ul[u] = jj + u < nch ? __builtin_amdgcn_readlane(dlen, q) : 0;
+                // jj + u <= 63; lanes at or past nch carry dbase = dlen = 0
+                ub[u] = __builtin_amdgcn_readlane(dbase, jj + u);
+                ul[u] = __builtin_amdgcn_readlane(dlen, jj + u);
             }
             // unconditional loads at a scalar base and the lane offset: lanes
             // past a chunk read up to 63 elements further (the column arrays
             // carry that much slack) and are masked below
 #pragma unroll
-            for (int u = 0; u < kHubUnroll; ++u) uw[u] = (col + ub[u])[(uint32_t)lane];
+            for (int u = 0; u < kHubUnroll; ++u) uw[u] = (col + (uint32_t)ub[u])[(uint32_t)lane];  // ub >= 0
             unsigned long long hb[kHubUnroll];
             if (MODE == kModeBitmap) {
                 // all chunks' bitmap words first (independent LDS reads), then
@@ -198,10 +199,11 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
                 for (int u = 0; u < kHubUnroll; ++u) {
                     const uint32_t bits = (uint32_t)bw[u];
                     const uint32_t bit = __builtin_amdgcn_ubfe(bits, off[u], 1u);
-                    // the mask of a lane compare (v_cmp), restricted to the chunk's lanes
-                    const unsigned long long valid = ul[u] >= 64 ? ~0ull : ((1ull << ul[u]) - 1ull);
-                    hb[u] = __builtin_amdgcn_uicmp(bit, 0u, 33 /* ne */) & valid;
-                    if (bit && lane < ul[u])
+                    // hit mask: two lane compares (v_cmp), the bit test and the chunk's lanes
+                    const bool in = (uint32_t)lane < (uint32_t)ul[u];
+                    hb[u] = __builtin_amdgcn_uicmp(bit, 0u, 33 /* ne */) &
+                            __builtin_amdgcn_uicmp((uint32_t)lane, (uint32_t)ul[u], 36 /* ult */);
+                    if (bit && in)
                         atomicAdd(&s_acc[(uint32_t)(bw[u] >> 32) + __popc(__builtin_amdgcn_ubfe(bits, 0u, off[u] & 31u))],
                                   1);
                 }
