@@ -91,7 +91,7 @@ struct HubItem {
 // Per-run scratch arrays inside the workspace.
 struct Scratch {
     int32_t* xscan;       // int32[m+1]: new CSR position of every old position
-    int32_t* cxscan;      // int32[m+1]: same for in-edge list entries
+    int32_t* cxscan;      // int32[m+1]: same for in-edge list entries when the lists are packed
     int32_t* blockcnt;    // int32[kMaxScanBlocks]
     int32_t* blockoff;    // int32[kMaxScanBlocks]
     int32_t* blockcnt2;   // int32[2*kMaxScanBlocks]

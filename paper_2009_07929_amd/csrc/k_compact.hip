@@ -355,7 +355,7 @@ hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* 
         run_filter(CsrAlive{x, y, alive_can}, ctl, p, 2, 0, sc.blockcnt, sc.blockoff, sc.xscan, m_hint, s);
     }
     k_ptr_remap<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(x.rowptr, y.rowptr, n, sc.xscan, ctl, round);
-    if (cx && csc_hint > 0) {  // the in-edge lists (remapped in place; cy is the same set) and alive in-edge counts
+    if (cx && csc_hint > 0) {  // the in-edge lists (one set: cy names the same arrays) and alive in-edge counts
         k_zero_rows<<<grid_for(n), kBlock, 0, s>>>(sc.alive_in, n, ctl, round);
         k_csc_remap<<<min(grid_for(csc_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(cx->edge, cx->key, sc.xscan,
                                                                                          sc.alive_in, ctl, round);

@@ -215,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_task_tails(Buf x, Csc c, const Ctl* 
 }
 
 // Alive in-edges of every row kappa at the start of a run: the list lengths.
-// The prune decrements them for every removed edge.
+// After every prune the in-place remap of the lists recounts them.
 __global__ __launch_bounds__(kBlock) void k_alive_in_init(const int32_t* __restrict__ cptr, int32_t n,
                                                         int32_t* __restrict__ alive_in) {
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
