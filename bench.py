@@ -94,6 +94,27 @@ def tuning(kt, rounds_per_sync):
     return t
 
 
+def first_pass(kt, torch, g, stream, reps=3):
+    """Round 1 alone: one support pass over the whole graph (ktruss_support),
+    profiled; the hub kernel's time per launch and the pass's merge-model
+    bytes (outside the timed region of the step)."""
+    sup = torch.empty(max(g.m, 1), dtype=torch.int32, device=g.device)
+    kt.ktruss_support(g, None, sup, stream)
+    torch.cuda.synchronize()
+    kt.ktruss_profile_enable(True)
+    for _ in range(reps):
+        kt.ktruss_support(g, None, sup, stream)
+    torch.cuda.synchronize()
+    launches, ms, _, nbytes = kt.ktruss_profile_read(kt.PROFILE_PASS)
+    hl, hms, _, _ = kt.ktruss_profile_read(kt.PROFILE_HUB)
+    kt.ktruss_profile_enable(False)
+    out = {"passes": launches, "pass_ms": ms / max(launches, 1), "bytes": nbytes / max(launches, 1)}
+    if hl == launches and hl:
+        out["hub_ms"] = hms / hl
+        out["achieved_gbps"] = out["bytes"] / (out["hub_ms"] * 1e-3) / 1e9
+    return out
+
+
 def single_sweep(args, kt, torch):
     """The main leg: K sweep on one large graph.  Returns the JSON dict."""
     import synth
@@ -177,6 +198,7 @@ def single_sweep(args, kt, torch):
     else:
         kernel, avg_launch_ms, traffic = "support pass", avg_pass_ms, None
     achieved = bytes_per_launch / (avg_launch_ms * 1e-3) / 1e9 if launches else 0.0
+    first = first_pass(kt, torch, g, stream)
     del g
     return {
         "metric": "edges processed/s per K + HBM GB/s; learned/batched vs plain GPU, bit-exact",
@@ -208,6 +230,7 @@ def single_sweep(args, kt, torch):
             "dram_gbps": (traffic / (avg_launch_ms * 1e-3) / 1e9) if traffic else None,
             "variants": kinds,
         },
+        "first_pass": first,
     }
 
 
