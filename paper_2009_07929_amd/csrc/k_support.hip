@@ -129,8 +129,9 @@ static_assert(64 % kHubUnroll == 0, "a step's chunk indices jj + u stay within t
 // the wave then processes the block kHubUnroll chunks per step, reading the
 // descriptors with readlane: the loads of a step are issued together and no
 // per-chunk bookkeeping runs on the scalar unit.  Each chunk's hit word goes
-// to its lane and is written once per block, with one store and one atomic
-// instruction.  In the bitmap case a label beyond row kappa is
+// to its lane and is written once per block with one store; the block's hit
+// counts of each task are summed across lanes and added to S(i, kappa) with
+// one atomic per task.  In the bitmap case a label beyond row kappa is
 // clamped onto a zero guard word, so a lookup needs no compare-and-select.
 template <int MODE>
 __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __restrict__ hitw, int64_t hit_stride,
@@ -250,8 +251,18 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
         const unsigned long long word = ((unsigned long long)word_hi << 32) | word_lo;
         // written once and read once by k_hit_sum: a streaming store keeps L2 for the tails
         if (dv && dc < kHitWords) __builtin_nontemporal_store(word, &hitw[hit_word_index(de, dc, hit_stride)]);
-        const int32_t cnt = __popcll(word);
-        if (dv && cnt) atomicAdd(&x.S[de], cnt);
+        // S(i, kappa): the block's chunks of one task sit on consecutive lanes; a
+        // segmented sum gives one atomic per task and block instead of one per chunk
+        const int32_t key = dv ? de : -1;
+        int32_t cnt = dv ? __popcll(word) : 0;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t u = __shfl_up(cnt, o);
+            const int32_t kk = __shfl_up(key, o);
+            if (lane >= o && kk == key) cnt += u;
+        }
+        const int32_t next_key = __shfl_down(key, 1);
+        if (dv && cnt && (lane == 63 || next_key != key)) atomicAdd(&x.S[de], cnt);
     }
 }
 
