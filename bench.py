@@ -17,6 +17,9 @@ inside the same line:
            m=8, K = 3, 6, 10: the learned schedule (trained cost model) next to
            the static degree heuristic, the all-hub schedule and the plain
            kernel, edges/s per K, results checked identical.
+  coarse:  the coarse-grained ablation (one thread per row, Algorithm 2's
+           granularity) next to the fine-grained thread-per-edge kernel and
+           the hub schedule on R-MAT scale 12 (K = 3..6) and scale 20 (K = 3).
 
 Prints one JSON line.  Only one GPU is used; --gpus above 1 exits.
 """
@@ -34,7 +37,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0
-SCHEDULES = {"plain": 0, "heuristic": 1, "learned": 2, "wave": 3, "hub": 4}
+SCHEDULES = {"plain": 0, "heuristic": 1, "learned": 2, "wave": 3, "hub": 4, "coarse": 5}
 
 
 def log(msg):
@@ -349,6 +352,54 @@ def learned_leg(args, kt, torch, workloads=("rmat-s22-ef16", "ba-4M-m8")):
     return out
 
 
+def coarse_leg(args, kt, torch, workloads=(("rmat-s12-ef8", None), ("rmat-s20-ef16", (3,)))):
+    """The coarse-grained ablation: one thread per row running its edge tasks
+    in turn (Algorithm 2's granularity) against the fine-grained thread-per-
+    edge kernel and the hub schedule, edges/s per K (median of three runs
+    unless one run takes over a second), results checked equal."""
+    import numpy as np
+    import synth
+    out = {}
+    stream = torch.cuda.current_stream()
+    for wname, Ks in workloads:
+        w = synth.WORKLOADS[wname]
+        Ks = Ks or w.Ks
+        n, s, d = synth.workload_pairs(wname)
+        rowptr, col, _ = kt.ktruss_build_csr(s, d, n)
+        del s, d
+        m = len(col)
+        g = kt.Graph(rowptr, col, device="cuda:0")
+        mask = torch.empty(max(m, 1), dtype=torch.uint8, device="cuda:0")
+        sup = torch.empty(max(m, 1), dtype=torch.int32, device="cuda:0")
+        res = {"n": n, "m": m, "Ks": list(Ks)}
+        digest = {}
+        for sname in ("coarse", "plain", "hub"):
+            kt.ktruss_set_schedule(g, SCHEDULES[sname], None, tuning(kt, 0))
+            per = {}
+            for K in Ks:
+                kt.ktruss_run(g, K, mask, sup, stream)  # warm-up
+                ts = []
+                while not ts or (len(ts) < 3 and ts[0] < 1.0):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, _, r = kt.ktruss_run(g, K, mask, sup, stream)
+                    torch.cuda.synchronize()
+                    ts.append(time.perf_counter() - t0)
+                dt = float(np.median(ts))
+                dg = (r, int(mask[:m].sum().item()), int(sup[:m].to(torch.int64).sum().item()))
+                if digest.setdefault(K, dg) != dg:
+                    raise RuntimeError("schedule %s disagrees on %s K=%d" % (sname, wname, K))
+                per[str(K)] = {"ms": dt * 1e3, "edges_per_s": m / dt, "rounds": r}
+            tot = sum(v["ms"] for v in per.values())
+            res[sname] = {"per_K": per, "edges_per_s": len(Ks) * m / (tot * 1e-3)}
+            log("coarse leg: %s %s %.3e edges/s" % (wname, sname, res[sname]["edges_per_s"]))
+        res["fine_vs_coarse"] = res["plain"]["edges_per_s"] / res["coarse"]["edges_per_s"]
+        res["hub_vs_coarse"] = res["hub"]["edges_per_s"] / res["coarse"]["edges_per_s"]
+        out[wname] = res
+        del g, mask, sup
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -362,8 +413,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="batched,learned",
-                    help="comma-separated extra legs to run after the main leg (batched, learned)")
+    ap.add_argument("--extras", default="batched,learned,coarse",
+                    help="comma-separated extra legs to run after the main leg (batched, learned, coarse)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched leg: ignore the autotuner's cached configuration")
     ap.add_argument("--batch-graphs", type=int, default=4096)
@@ -396,7 +447,7 @@ def main():
         del a, b
 
     extras = set() if args.no_extras else {e for e in args.extras.split(",") if e}
-    unknown = extras - {"batched", "learned"}
+    unknown = extras - {"batched", "learned", "coarse"}
     if unknown:
         raise SystemExit("unknown extra legs: %s" % ",".join(sorted(unknown)))
     if "batched" in extras:
@@ -405,6 +456,9 @@ def main():
     if "learned" in extras:
         log("learned-schedule leg ...")
         out["learned"] = learned_leg(args, kt, torch)
+    if "coarse" in extras:
+        log("coarse-grained ablation leg ...")
+        out["coarse"] = coarse_leg(args, kt, torch)
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")

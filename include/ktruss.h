@@ -55,6 +55,9 @@ extern "C" {
 #define KTRUSS_SCHED_LEARNED    2  /* MLP cost model bins rows/edges (falls back to HEURISTIC without weights) */
 #define KTRUSS_SCHED_FORCE_WAVE 3  /* every edge task on the wavefront-per-edge kernel (testing) */
 #define KTRUSS_SCHED_FORCE_HUB  4  /* every row on the workgroup-per-row kernel (testing) */
+#define KTRUSS_SCHED_COARSE     5  /* one thread per row running its edge tasks in turn: the coarse granularity of
+                                      Section III-A's Algorithm 2 (with Algorithm 3's updates of all three
+                                      edges), kept as the ablation of the fine-grained path */
 
 /* Tuning knobs (0 = library default). */
 typedef struct ktruss_tuning {
@@ -230,7 +233,8 @@ int32_t ktruss_set_schedule(ktruss_graph* g, int32_t mode, const float* mlp_para
  *   1  thread-per-edge launches, 2 wavefront-per-edge launches, 3 hub-row
  *      launches (tasks = edge tasks, or hub items for kind 3);
  *   4  the row-local sum that adds the hub kernel's per-task hit words to
- *      S(i, w) (tasks = alive edges).
+ *      S(i, w) (tasks = alive edges);
+ *   5  thread-per-row launches of the coarse schedule (tasks = alive edges).
  * Enabling (or disabling) clears the tallies.  Returns KTRUSS_OK.
  */
 int32_t ktruss_profile_enable(int32_t on);
@@ -242,7 +246,7 @@ int32_t ktruss_profile_enable(int32_t on);
  * 8 (2 T + m) bytes of support read-modify-writes, with m the alive edges, W
  * the sum over them of |tail of the edge in its row| + |row kappa| and T the
  * triangles (the sum of the supports over 3), summed over the passes.
- * Any out pointer may be NULL.  E_INVALID for a kind outside 0..4.
+ * Any out pointer may be NULL.  E_INVALID for a kind outside 0..5.
  */
 int32_t ktruss_profile_read(int32_t kind, int64_t* launches, double* total_ms, int64_t* tasks, int64_t* bytes);
 

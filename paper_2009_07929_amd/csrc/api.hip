@@ -166,7 +166,7 @@ int32_t check_sizes(int32_t n, int64_t m) {
 }
 
 int32_t check_schedule(int32_t sched) {
-    if (sched < KTRUSS_SCHED_PLAIN || sched > KTRUSS_SCHED_FORCE_HUB)
+    if (sched < KTRUSS_SCHED_PLAIN || sched > KTRUSS_SCHED_COARSE)
         return fail(KTRUSS_E_INVALID, "unknown schedule %d", sched);
     return KTRUSS_OK;
 }
@@ -219,8 +219,8 @@ int32_t validate_on_device(const int32_t* rowptr, const int32_t* col, int32_t n,
 
 // ---- profiling tallies (process-wide; guarded by a mutex)
 // kinds: 0 whole support pass, 1 thread-per-edge, 2 wavefront-per-edge, 3 hub,
-// 4 row-local sum of the hub hit words
-constexpr int kKinds = 5;
+// 4 row-local sum of the hub hit words, 5 thread-per-row (coarse schedule)
+constexpr int kKinds = 6;
 struct Rec {
     int kind;
     hipEvent_t e0, e1;
@@ -307,7 +307,9 @@ unsigned long long* profile_work() {
     return P.on ? P.work_dev : nullptr;
 }
 
-bool uses_csc(int sched) { return sched != KTRUSS_SCHED_PLAIN && sched != KTRUSS_SCHED_FORCE_WAVE; }
+bool uses_csc(int sched) {
+    return sched != KTRUSS_SCHED_PLAIN && sched != KTRUSS_SCHED_FORCE_WAVE && sched != KTRUSS_SCHED_COARSE;
+}
 
 // Light-graph gate of the heuristic and learned schedules: an input whose
 // mean merge length per edge (row tails exact, row-kappa lengths sampled on
@@ -345,6 +347,8 @@ int32_t support_pass(int sched, int32_t n, const Work& w, int p, const PassDims&
         rc = timed_launch(1, dm.m, s, [&] {
             return launch_support_thread(x, nullptr, &w.ctl->m_buf[p], dm.m, w.ctl, s);
         });
+    } else if (sched == KTRUSS_SCHED_COARSE) {
+        rc = timed_launch(5, dm.m, s, [&] { return launch_support_row(x, n, w.ctl, s); });
     } else if (sched == KTRUSS_SCHED_FORCE_WAVE) {
         rc = timed_launch(2, dm.m, s, [&] {
             return launch_support_wave(x, nullptr, &w.ctl->m_buf[p], dm.m, w.ctl, s);

@@ -52,6 +52,7 @@ hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched,
 // ---- support kernels (k_support.hip); count_dev points at the task count
 hipError_t launch_support_thread(const Buf& x, const int32_t* tasks, const int32_t* count_dev, int32_t n_hint,
                                  const Ctl* ctl, hipStream_t s);
+hipError_t launch_support_row(const Buf& x, int32_t n, const Ctl* ctl, hipStream_t s);
 hipError_t launch_support_wave(const Buf& x, const int32_t* tasks, const int32_t* count_dev, int32_t n_hint,
                                const Ctl* ctl, hipStream_t s);
 // cycles: per-row shader-clock totals of the hub items (cost-model samples), or null

@@ -17,7 +17,7 @@ from . import build as _build
 
 # status codes (include/ktruss.h)
 OK, E_INVALID, E_OVERFLOW, E_CAPACITY, E_HIP, E_NOMEM = 0, -1, -2, -3, -4, -5
-SCHED_PLAIN, SCHED_HEURISTIC, SCHED_LEARNED, SCHED_FORCE_WAVE, SCHED_FORCE_HUB = 0, 1, 2, 3, 4
+SCHED_PLAIN, SCHED_HEURISTIC, SCHED_LEARNED, SCHED_FORCE_WAVE, SCHED_FORCE_HUB, SCHED_COARSE = 0, 1, 2, 3, 4, 5
 
 _lib = None
 
@@ -199,7 +199,7 @@ def ktruss_profile_enable(on: bool = True):
     _check(load().ktruss_profile_enable(1 if on else 0))
 
 
-PROFILE_PASS, PROFILE_THREAD, PROFILE_WAVE, PROFILE_HUB, PROFILE_HIT_SUM = 0, 1, 2, 3, 4
+PROFILE_PASS, PROFILE_THREAD, PROFILE_WAVE, PROFILE_HUB, PROFILE_HIT_SUM, PROFILE_ROW = 0, 1, 2, 3, 4, 5
 
 
 def ktruss_profile_read(kind: int = PROFILE_PASS):

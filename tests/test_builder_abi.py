@@ -120,6 +120,9 @@ def test_argument_errors_before_any_hip_call():
     assert lib.ktruss_run(G(g5), 3, 16, 16, None, None) == kt.E_OVERFLOW
     assert lib.ktruss_prune(G(host_graph()), 1, 16, 16, None, None) == kt.E_INVALID
     assert lib.ktruss_set_schedule(G(host_graph()), 9, None, None) == kt.E_INVALID
+    assert lib.ktruss_set_schedule(G(host_graph()), kt.SCHED_COARSE + 1, None, None) == kt.E_INVALID
+    assert lib.ktruss_set_schedule(G(host_graph()), kt.SCHED_COARSE, None, None) == 0
+    assert lib.ktruss_profile_read(kt.PROFILE_ROW + 1, None, None, None, None) == kt.E_INVALID
     assert lib.ktruss_set_schedule(None, 0, None, None) == kt.E_INVALID
     g6 = host_graph()
     g6.work = 257                                                                   # misaligned workspace

@@ -9,7 +9,7 @@ from conftest import gpu_available
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(not gpu_available(), reason="needs a GPU")]
 
-SCHEDULES = [0, 1, 3, 4]
+SCHEDULES = [0, 1, 3, 4, 5]  # plain, heuristic, force-wave, force-hub, coarse
 
 
 def kt():

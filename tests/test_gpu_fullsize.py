@@ -55,7 +55,7 @@ def s20():
     return rp, col, n2o
 
 
-@pytest.mark.parametrize("schedule", [0, 1, 4])
+@pytest.mark.parametrize("schedule", [0, 1, 4, 5])
 def test_rmat20_digests(schedule, s20):
     import torch
     rp, col, n2o = s20

@@ -57,7 +57,7 @@ def test_small_graphs(name):
         assert_parity(rp, col, K, label=name)
 
 
-SCHEDULES = [0, 1, 3, 4]   # plain, heuristic, force-wave, force-hub
+SCHEDULES = [0, 1, 3, 4, 5]   # plain, heuristic, force-wave, force-hub, coarse (thread per row)
 
 
 @pytest.mark.parametrize("schedule", SCHEDULES)
