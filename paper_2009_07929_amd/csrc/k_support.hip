@@ -59,19 +59,6 @@ __device__ __forceinline__ void thread_task(const Buf& x, int32_t e) {
     if (cnt) atomicAdd(&x.S[e], cnt);
 }
 
-// ------------------------------------------------ thread-per-row (coarse)
-// One thread per row i running the tasks of its edges one after the other:
-// the one-task-per-row granularity of Algorithm 2, with the merge and the
-// updates of all three edges of thread_task (Algorithm 3's).  The coarse
-// ablation of the fine-grained kernels.
-__global__ __launch_bounds__(kBlock) void k_support_row(Buf x, int32_t n, const Ctl* __restrict__ ctl) {
-    if (ctl->done) return;
-    for (int32_t i = (int32_t)(blockIdx.x * kBlock + threadIdx.x); i < n; i += (int32_t)(gridDim.x * kBlock)) {
-        const int32_t re = x.rowptr[i + 1];
-        for (int32_t e = x.rowptr[i]; e < re; ++e) thread_task(x, e);
-    }
-}
-
 // ---------------------------------------------------- wavefront-per-edge
 // One wave per task.  The 64 lanes walk the shorter of the two lists and
 // binary-search each element in the other (both ascending, in global memory;
@@ -495,12 +482,6 @@ hipError_t launch_support_thread(const Buf& x, const int32_t* tasks, const int32
                                  const Ctl* ctl, hipStream_t s) {
     if (n_hint <= 0) return hipSuccess;
     k_support_thread<<<min(grid_for(n_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, tasks, count_dev, ctl);
-    return hipGetLastError();
-}
-
-hipError_t launch_support_row(const Buf& x, int32_t n, const Ctl* ctl, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    k_support_row<<<min(grid_for(n), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, n, ctl);
     return hipGetLastError();
 }
 
