@@ -177,6 +177,22 @@ int32_t ktruss_prune(const ktruss_graph* g, int32_t K, const int32_t* support, u
 int32_t ktruss_run(const ktruss_graph* g, int32_t K, uint8_t* mask, int32_t* support,
                    int32_t* rounds, void* stream);
 
+/*
+ * ktruss_decompose — the trussness of every edge (the K_max analysis of
+ * Section IV, for all edges at once): the largest K whose K-truss holds the
+ * edge.  Since the (K+1)-truss lies inside the K-truss, each level starts from
+ * the previous level's survivors and their supports (already exact for that
+ * subgraph): it prunes with the new threshold, and recomputes supports only
+ * when something was removed, until the fixpoint.
+ *   trussness  device int32[m] out: 2 for an edge in no triangle, else the
+ *              largest K >= 3 with the edge in the K-truss.
+ *   k_max      host int32 out: the largest trussness (0 for a graph with no
+ *              edges): the largest K with a non-empty K-truss.
+ * Equal, bit for bit, to the largest K at which ktruss_run keeps the edge.
+ * Uses the graph's schedule (host-checked rounds).  Synchronises `stream`.
+ */
+int32_t ktruss_decompose(const ktruss_graph* g, int32_t* trussness, int32_t* k_max, void* stream);
+
 /* ----------------------------------------------------------- batched form */
 /*
  * Many independent graphs in one fixpoint loop.  The graphs are concatenated

@@ -738,6 +738,65 @@ int32_t ktruss_run(const ktruss_graph* g, int32_t K, uint8_t* mask, int32_t* sup
     return KTRUSS_OK;
 }
 
+int32_t ktruss_decompose(const ktruss_graph* g, int32_t* trussness, int32_t* k_max, void* stream) {
+    clear_error();
+    int32_t rc = check_graph(g, true);
+    if (rc != KTRUSS_OK) return rc;
+    if (!k_max) return fail(KTRUSS_E_INVALID, "k_max is null");
+    if (g->m > 0 && !trussness) return fail(KTRUSS_E_INVALID, "trussness is null");
+    hipStream_t s = (hipStream_t)stream;
+    Work w = carve(g->work, g->n, g->m, 0);
+    const int32_t n = g->n, m = (int32_t)g->m;
+    unsigned long long merge_work = 0;
+    rc = validate_on_device(g->rowptr, g->col, n, m, w, w.b[0].src, s, gated(g) ? &merge_work : nullptr);
+    if (rc != KTRUSS_OK) return rc;
+    *k_max = 0;
+    if (m == 0) return KTRUSS_OK;
+    RunSpec r = make_spec(n, m, g->rowptr, g->col, schedule_for(g, merge_work), g->tuning, g->mlp_params);
+    r.tuning.rounds_per_sync = 0;  // host-checked rounds: each level ends on the host
+    r.thr = 1;                     // K = 3
+    rc = set_up_run(r, w, s);
+    if (rc != KTRUSS_OK) return rc;
+    HIP_TRY(launch_fill_value(trussness, m, 2, s), "trussness fill");
+    rc = prepare(r, w, 0, m, s);
+    Ctl h{};
+    if (rc == KTRUSS_OK) rc = run_rounds(r, w, s, h);
+    if (rc != KTRUSS_OK) return rc;
+    for (int32_t K = 3;; ++K) {
+        const int f = h.final_buf;
+        const int32_t mf = h.m_buf[f];
+        if (mf == 0) {
+            *k_max = K - 1;
+            break;
+        }
+        HIP_TRY(launch_mark_level(w.b[f], w.ctl, f, mf, K, trussness, s), "level marks");
+        // level K + 1 from the survivors of level K: prune with the new
+        // threshold (their supports are exact), then rounds until the fixpoint
+        r.thr = K - 1;
+        HIP_TRY(launch_ctl_restart(w.ctl, s), "level restart");
+        const bool csc = uses_csc(r.sched);
+        HIP_TRY(launch_compact(w.b[f], w.b[1 - f], csc ? &w.c[f] : nullptr, csc ? &w.c[1 - f] : nullptr, r.n, 0, r.thr,
+                               nullptr, w.batch, w.sc, w.ctl, f, mf, r.m, s),
+                "level prune");
+        rc = prepare(r, w, 1 - f, mf, s);
+        if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
+        if (rc != KTRUSS_OK) return rc;
+        int p = 1 - f;
+        int32_t m_hint = h.m_buf[p];
+        while (!h.done) {  // something was removed: recompute from buffer p
+            const PassDims dm{m_hint, h.n_items, h.n_wave, h.n_thread};
+            rc = enqueue_round(r, w, p, dm, s);
+            if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
+            if (rc != KTRUSS_OK) return rc;
+            if (h.done) break;
+            m_hint = h.m_buf[1 - p];
+            p ^= 1;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(s), "decompose sync");
+    return KTRUSS_OK;
+}
+
 int32_t ktruss_run_batched(const ktruss_batch* b, const int32_t* K, uint8_t* mask, int32_t* support,
                            int32_t* rounds, void* stream) {
     clear_error();

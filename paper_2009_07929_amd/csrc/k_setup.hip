@@ -101,6 +101,24 @@ __global__ __launch_bounds__(kBlock) void k_init_eid_s(int32_t* __restrict__ eid
     }
 }
 
+// Survivors of a decomposition level (buffer f of the fixpoint) get trussness K.
+__global__ __launch_bounds__(kBlock) void k_mark_level(Buf b, const Ctl* __restrict__ ctl, int f, int32_t K,
+                                                     int32_t* __restrict__ trussness) {
+    const int32_t e = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (e < ctl->m_buf[f]) trussness[b.eid[e]] = K;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_value(int32_t* __restrict__ a, int32_t n, int32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) a[i] = v;
+}
+
+// Next decomposition level: the fixpoint flag is cleared so that the rounds
+// continue from the final buffer.
+__global__ void k_ctl_restart(Ctl* ctl) {
+    if (threadIdx.x == 0) ctl->done = 0;
+}
+
 __global__ void k_set_final(Ctl* ctl, int f) {
     if (threadIdx.x == 0) ctl->final_buf = f;
 }
@@ -160,6 +178,24 @@ hipError_t launch_init_run(const Buf& b, const int32_t* rowptr, const int32_t* c
         if (e != hipSuccess) return e;
         k_init_eid_s<<<grid_for(m), kBlock, 0, s>>>(b.eid, b.S, m);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_mark_level(const Buf& b, const Ctl* ctl, int f, int32_t m_hint, int32_t K, int32_t* trussness,
+                             hipStream_t s) {
+    if (m_hint <= 0) return hipSuccess;
+    k_mark_level<<<grid_for(m_hint), kBlock, 0, s>>>(b, ctl, f, K, trussness);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_value(int32_t* a, int32_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    k_fill_value<<<grid_for(n), kBlock, 0, s>>>(a, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_ctl_restart(Ctl* ctl, hipStream_t s) {
+    k_ctl_restart<<<1, 64, 0, s>>>(ctl);
     return hipGetLastError();
 }
 

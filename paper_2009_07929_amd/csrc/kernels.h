@@ -12,6 +12,10 @@ hipError_t launch_validate(const int32_t* rowptr, const int32_t* col, int32_t n,
 hipError_t launch_init_run(const Buf& b, const int32_t* rowptr, const int32_t* col, int32_t n, int32_t m,
                            hipStream_t s);
 hipError_t launch_set_final(Ctl* ctl, int f, hipStream_t s);
+hipError_t launch_mark_level(const Buf& b, const Ctl* ctl, int f, int32_t m_hint, int32_t K, int32_t* trussness,
+                             hipStream_t s);
+hipError_t launch_fill_value(int32_t* a, int32_t n, int32_t v, hipStream_t s);
+hipError_t launch_ctl_restart(Ctl* ctl, hipStream_t s);
 hipError_t launch_scatter_out(const Buf& b0, const Buf& b1, const Ctl* ctl, uint8_t* mask, int32_t* support,
                               int32_t m_hint, hipStream_t s);
 hipError_t launch_prune_canonical(const int32_t* support, uint8_t* alive, int32_t m, int32_t thr,

@@ -69,6 +69,7 @@ def load():
         "ktruss_support": ([G, p, p, p], i32),
         "ktruss_prune": ([G, i32, p, p, p, p], i32),
         "ktruss_run": ([G, i32, p, p, p, p], i32),
+        "ktruss_decompose": ([G, p, p, p], i32),
         "ktruss_set_schedule": ([G, i32, p, ctypes.POINTER(ktruss_tuning)], i32),
         "ktruss_profile_enable": ([i32], i32),
         "ktruss_profile_read": ([i32, p, p, p, p], i32),
@@ -222,6 +223,16 @@ def ktruss_run(g: Graph, K: int, mask=None, support=None, stream=None):
     _check(load().ktruss_run(ctypes.byref(g.c), K, _ptr(mask), _ptr(support), ctypes.byref(rounds),
                              _stream(stream)))
     return mask[: g.m], support[: g.m], rounds.value
+
+
+def ktruss_decompose(g: Graph, trussness=None, stream=None):
+    """Trussness of every edge.  Returns (trussness int32[m], k_max)."""
+    import torch
+    if trussness is None:
+        trussness = torch.empty(max(g.m, 1), dtype=torch.int32, device=g.device)
+    k_max = ctypes.c_int32()
+    _check(load().ktruss_decompose(ctypes.byref(g.c), _ptr(trussness), ctypes.byref(k_max), _stream(stream)))
+    return trussness[: g.m], k_max.value
 
 
 # ------------------------------------------------------------------ batched form

@@ -124,6 +124,10 @@ def test_argument_errors_before_any_hip_call():
     assert lib.ktruss_set_schedule(G(host_graph()), kt.SCHED_COARSE, None, None) == 0
     assert lib.ktruss_profile_read(kt.PROFILE_ROW + 1, None, None, None, None) == kt.E_INVALID
     assert lib.ktruss_set_schedule(None, 0, None, None) == kt.E_INVALID
+    assert lib.ktruss_decompose(None, 16, 16, None) == kt.E_INVALID
+    assert lib.ktruss_decompose(G(host_graph()), 16, None, None) == kt.E_INVALID     # null k_max
+    assert lib.ktruss_decompose(G(host_graph()), None, 16, None) == kt.E_INVALID     # null trussness
+    assert lib.ktruss_decompose(G(host_graph(work_bytes=10)), 16, 16, None) == kt.E_CAPACITY
     g6 = host_graph()
     g6.work = 257                                                                   # misaligned workspace
     assert lib.ktruss_validate(G(g6), None) == kt.E_INVALID
