@@ -20,6 +20,8 @@ inside the same line:
   coarse:  the coarse-grained ablation (one thread per row, Algorithm 2's
            granularity) next to the fine-grained thread-per-edge kernel and
            the hub schedule on R-MAT scale 12 (K = 3..6) and scale 20 (K = 3).
+  decompose: every edge's trussness on R-MAT scale 20 in one call, next to
+           the same levels computed one K at a time from the full graph.
 
 Prints one JSON line.  Only one GPU is used; --gpus above 1 exits.
 """
@@ -400,6 +402,49 @@ def coarse_leg(args, kt, torch, workloads=(("rmat-s12-ef8", None), ("rmat-s20-ef
     return out
 
 
+def decompose_leg(args, kt, torch, wname="rmat-s20-ef16"):
+    """Truss decomposition (every edge's trussness, K_max) in one call, next
+    to the same trusses computed one K at a time from the full graph
+    (ktruss_run for K = 3 .. K_max + 1); the trussness is checked against
+    those runs."""
+    import numpy as np
+    import synth
+    n, s, d = synth.workload_pairs(wname)
+    rowptr, col, _ = kt.ktruss_build_csr(s, d, n)
+    del s, d
+    m = len(col)
+    g = kt.Graph(rowptr, col, device="cuda:0")
+    kt.ktruss_set_schedule(g, SCHEDULES[args.schedule], None, tuning(kt, 0))
+    stream = torch.cuda.current_stream()
+    tr = torch.empty(m, dtype=torch.int32, device="cuda:0")
+    kt.ktruss_decompose(g, tr, stream)  # warm-up
+    ts = []
+    while not ts or (len(ts) < 3 and ts[0] < 1.0):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, k_max = kt.ktruss_decompose(g, tr, stream)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    t_dec = float(np.median(ts))
+    # the same levels one K at a time, each from the full graph
+    mask = torch.empty(m, dtype=torch.uint8, device="cuda:0")
+    sup = torch.empty(m, dtype=torch.int32, device="cuda:0")
+    level = torch.full((m,), 2, dtype=torch.int32, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for K in range(3, k_max + 2):
+        kt.ktruss_run(g, K, mask, sup, stream)
+        level[mask.bool()] = K
+    torch.cuda.synchronize()
+    t_each = time.perf_counter() - t0
+    agree = bool(torch.equal(level, tr))
+    if not agree:
+        raise RuntimeError("decomposition disagrees with the per-K runs on %s" % wname)
+    del g
+    return {"workload": wname, "m": m, "k_max": k_max, "decompose_ms": t_dec * 1e3, "edges_per_s": m / t_dec,
+            "per_K_runs_ms": t_each * 1e3, "speedup_vs_per_K_runs": t_each / t_dec, "agree": agree}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -413,8 +458,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--no-extras", action="store_true")
-    ap.add_argument("--extras", default="batched,learned,coarse",
-                    help="comma-separated extra legs to run after the main leg (batched, learned, coarse)")
+    ap.add_argument("--extras", default="batched,learned,coarse,decompose",
+                    help="comma-separated extra legs to run after the main leg (batched, learned, coarse, decompose)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched leg: ignore the autotuner's cached configuration")
     ap.add_argument("--batch-graphs", type=int, default=4096)
@@ -447,7 +492,7 @@ def main():
         del a, b
 
     extras = set() if args.no_extras else {e for e in args.extras.split(",") if e}
-    unknown = extras - {"batched", "learned", "coarse"}
+    unknown = extras - {"batched", "learned", "coarse", "decompose"}
     if unknown:
         raise SystemExit("unknown extra legs: %s" % ",".join(sorted(unknown)))
     if "batched" in extras:
@@ -459,6 +504,9 @@ def main():
     if "coarse" in extras:
         log("coarse-grained ablation leg ...")
         out["coarse"] = coarse_leg(args, kt, torch)
+    if "decompose" in extras:
+        log("truss decomposition leg ...")
+        out["decompose"] = decompose_leg(args, kt, torch)
     out["cpu_baseline"] = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
