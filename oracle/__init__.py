@@ -8,8 +8,9 @@ product package.
 
 Tiers:
   * ``ktruss_oracle.c`` (loaded via ctypes): canonical CSR from raw pairs;
-    one support evaluation; the truss by literal Algorithm 1 recompute
-    (mode "R") and by level-synchronous peeling (mode "P").
+    one support evaluation (of every edge, or of listed edges); the truss by
+    literal Algorithm 1 recompute (mode "R") and by level-synchronous peeling
+    (mode "P").
   * pure-Python brute force for tiny graphs (every vertex tested as the third
     corner of every edge) and exhaustive maximality over all edge subsets.
   * ``mlp`` (float64 NumPy): the cost-model network's forward, backward and
@@ -50,7 +51,9 @@ def _load():
         lib.orc_supports.argtypes = [i32, p, p, p, p]
         lib.orc_truss_recompute.argtypes = [i32, p, p, i32, p, p, p, p]
         lib.orc_truss_peel.argtypes = [i32, p, p, i32, p, p, p, p]
-        for f in (lib.orc_canonical_csr, lib.orc_supports, lib.orc_truss_recompute, lib.orc_truss_peel):
+        lib.orc_supports_of.argtypes = [i32, p, p, p, i64, p, p]
+        for f in (lib.orc_canonical_csr, lib.orc_supports, lib.orc_truss_recompute, lib.orc_truss_peel,
+                  lib.orc_supports_of):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -93,6 +96,21 @@ def supports(rowptr, col, alive=None):
     if rc != 0:
         raise OracleError("orc_supports: %d" % rc)
     return out[: len(col)]
+
+
+def supports_of(rowptr, col, edges, timed: bool = False):
+    """Supports (triangles containing the edge, whole graph alive) of the listed
+    edge positions; with timed=True also the seconds of the per-edge loop."""
+    n = len(rowptr) - 1
+    rowptr = np.ascontiguousarray(rowptr, np.int32)
+    col = np.ascontiguousarray(col, np.int32)
+    edges = np.ascontiguousarray(edges, np.int64)
+    out = np.zeros(max(len(edges), 1), np.int32)
+    ns = ctypes.c_int64()
+    rc = _load().orc_supports_of(n, _p(rowptr), _p(col), _p(edges), len(edges), _p(out), ctypes.addressof(ns))
+    if rc != 0:
+        raise OracleError("orc_supports_of: %d" % rc)
+    return (out[: len(edges)], ns.value * 1e-9) if timed else out[: len(edges)]
 
 
 def truss(rowptr, col, K: int, mode: str = "P", alive_init=None):

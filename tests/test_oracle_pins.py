@@ -305,3 +305,45 @@ def test_canonical_csr_properties():
             assert (np.diff(deg) <= 0).all()
         if order == 0:
             assert (n2o == np.arange(n)).all()
+
+
+def test_canonical_relabel_tie_break():
+    """Equal-degree vertices take consecutive new labels in ascending original
+    id (ascending order), and in ascending original id too under the
+    descending order: the relabelling is the stable sort of the vertices by
+    degree.  A hand-made graph whose degree classes interleave the ids."""
+    # degrees by original id: 0:1 1:3 2:1 3:2 4:3 5:2 6:0 7:2 (stars and paths)
+    pairs = [(1, 0), (1, 2), (1, 3), (4, 3), (4, 5), (4, 7), (5, 7)]
+    s = np.array([a for a, _ in pairs], np.int32)
+    d = np.array([b for _, b in pairs], np.int32)
+    _, _, n2o_up = oracle.canonical_csr(8, s, d, 1)
+    assert n2o_up.tolist() == [6, 0, 2, 3, 5, 7, 1, 4]
+    _, _, n2o_down = oracle.canonical_csr(8, s, d, 2)
+    assert n2o_down.tolist() == [1, 4, 3, 5, 7, 0, 2, 6]
+    # the same rule on a random graph, written as a stable sort by degree
+    n, rs, rd = synth.raw_noise(400, 1500, 11)
+    keep = rs != rd
+    deg = np.zeros(n, np.int64)
+    e = {(min(a, b), max(a, b)) for a, b in zip(rs[keep].tolist(), rd[keep].tolist())}
+    for a, b in e:
+        deg[a] += 1
+        deg[b] += 1
+    assert oracle.canonical_csr(n, rs, rd, 1)[2].tolist() == np.argsort(deg, kind="stable").tolist()
+    assert oracle.canonical_csr(n, rs, rd, 2)[2].tolist() == np.argsort(-deg, kind="stable").tolist()
+
+
+def test_supports_of_listed_edges_match_scipy(rmat12):
+    """The listed-edge support evaluation (used to time the oracle on a sample
+    of a large graph) equals SciPy's (A A) o A at those edges."""
+    n, s, d = rmat12
+    rp, col, _ = oracle.canonical_csr(n, s, d)
+    m = len(col)
+    rows = np.repeat(np.arange(n), np.diff(rp))
+    A = sp.coo_matrix((np.ones(m, np.int64), (rows, col)), shape=(n, n)).tocsr()
+    A = A + A.T
+    S = (A @ A).multiply(A).tocsr()
+    edges = np.random.default_rng(3).choice(m, 500, replace=False)
+    got, secs = oracle.supports_of(rp, col, edges, timed=True)
+    want = np.asarray(S[rows[edges], col[edges]]).ravel()
+    assert np.array_equal(got, want) and secs >= 0.0
+    assert len(oracle.supports_of(rp, col, np.zeros(0, np.int64))) == 0
