@@ -113,7 +113,7 @@ extern "C" int32_t ktruss_build_csr(const int32_t* src, const int32_t* dst, int6
             col[i] = (int32_t)(key[i] % un);
         }
         for (int32_t v = 0; v < n; ++v) rowptr[v + 1] += rowptr[v];
-        if (new_to_old) std::memcpy(new_to_old, n2o.data(), sizeof(int32_t) * (size_t)n);
+        if (new_to_old && n > 0) std::memcpy(new_to_old, n2o.data(), sizeof(int32_t) * (size_t)n);
         return KTRUSS_OK;
     } catch (const std::bad_alloc&) {
         return kt::fail(KTRUSS_E_NOMEM, "host allocation failed while building the CSR");
