@@ -13,6 +13,9 @@ Tiers:
     (mode "P").
   * pure-Python brute force for tiny graphs (every vertex tested as the third
     corner of every edge) and exhaustive maximality over all edge subsets.
+  * ``butterfly_oracle.c``: butterflies (4-cycles) of a bipartite graph per
+    edge and in total, from the common-neighbour definition; a pure-Python
+    brute force over all 4-tuples for tiny graphs.
   * ``mlp`` (float64 NumPy): the cost-model network's forward, backward and
     optimizer step, checked by finite differences in the tests.
 """
@@ -27,6 +30,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "ktruss_oracle.c")
+_SRC_BFLY = os.path.join(_HERE, "butterfly_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -35,7 +39,7 @@ def build(force: bool = True) -> str:
     """Compile the C oracle with gcc (plain C99, -O2, no vectorisation pragmas)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", _SRC, "-o", tmp])
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", _SRC, _SRC_BFLY, "-o", tmp])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -52,8 +56,9 @@ def _load():
         lib.orc_truss_recompute.argtypes = [i32, p, p, i32, p, p, p, p]
         lib.orc_truss_peel.argtypes = [i32, p, p, i32, p, p, p, p]
         lib.orc_supports_of.argtypes = [i32, p, p, p, i64, p, p]
+        lib.orc_butterflies.argtypes = [i32, i32, p, p, p, p]
         for f in (lib.orc_canonical_csr, lib.orc_supports, lib.orc_truss_recompute, lib.orc_truss_peel,
-                  lib.orc_supports_of):
+                  lib.orc_supports_of, lib.orc_butterflies):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -128,6 +133,37 @@ def truss(rowptr, col, K: int, mode: str = "P", alive_init=None):
     if rc != 0:
         raise OracleError("orc_truss_%s: %d" % (mode, rc))
     return mask[:m], sup[:m], rounds.value
+
+
+def butterflies(nu: int, nv: int, rowptr, col):
+    """Butterflies (4-cycles) of a bipartite graph given as CSR rows over U with
+    columns in [0, nv): (count int64[m] per edge, total)."""
+    rowptr = np.ascontiguousarray(rowptr, np.int32)
+    col = np.ascontiguousarray(col, np.int32)
+    count = np.zeros(max(len(col), 1), np.int64)
+    total = ctypes.c_int64()
+    rc = _load().orc_butterflies(int(nu), int(nv), _p(rowptr), _p(col), _p(count), ctypes.addressof(total))
+    if rc != 0:
+        raise OracleError("orc_butterflies: %d" % rc)
+    return count[: len(col)], total.value
+
+
+def butterflies_bruteforce(nu: int, nv: int, edges):
+    """Every 4-tuple u1 < u2, v1 < v2 tried against the edge set (tiny graphs).
+    edges: list of (u, v).  Returns (count per edge in the given order, total)."""
+    es = set(edges)
+    cnt = {e: 0 for e in edges}
+    total = 0
+    for u1 in range(nu):
+        for u2 in range(u1 + 1, nu):
+            for v1 in range(nv):
+                for v2 in range(v1 + 1, nv):
+                    quad = [(u1, v1), (u1, v2), (u2, v1), (u2, v2)]
+                    if all(q in es for q in quad):
+                        total += 1
+                        for q in quad:
+                            cnt[q] += 1
+    return [cnt[e] for e in edges], total
 
 
 def prune(support, alive, K: int):

@@ -117,6 +117,30 @@ def barabasi_albert(n: int, m: int, seed: int):
     return n, src, dst
 
 
+def bipartite_chung_lu(nu: int, nv: int, gamma_u: float, gamma_v: float, npairs: int, seed: int):
+    """Bipartite pairs (u in [0, nu), v in [0, nv)) with power-law expected
+    degrees on both sides: each of the npairs draws picks u with probability
+    proportional to (u + 1)^(-1 / (gamma_u - 1)) and v likewise with gamma_v
+    (repeated pairs possible; the builders drop them).  Returns (nu, nv, u, v)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    wu = (np.arange(nu, dtype=np.float64) + 1.0) ** (-1.0 / (gamma_u - 1.0))
+    wv = (np.arange(nv, dtype=np.float64) + 1.0) ** (-1.0 / (gamma_v - 1.0))
+    cu, cv = np.cumsum(wu), np.cumsum(wv)
+    u = np.searchsorted(cu, rng.random(npairs) * cu[-1], side="right")
+    v = np.searchsorted(cv, rng.random(npairs) * cv[-1], side="right")
+    return nu, nv, np.minimum(u, nu - 1).astype(np.int32), np.minimum(v, nv - 1).astype(np.int32)
+
+
+def bipartite_csr(nu: int, nv: int, u, v):
+    """Rows over U with ascending, distinct columns (plain NumPy, for tests):
+    (rowptr int32[nu+1], col int32[m])."""
+    key = np.unique(np.asarray(u, np.int64) * nv + np.asarray(v, np.int64))
+    rows, cols = key // nv, key % nv
+    rowptr = np.zeros(nu + 1, np.int64)
+    np.add.at(rowptr, rows + 1, 1)
+    return np.cumsum(rowptr).astype(np.int32), cols.astype(np.int32)
+
+
 # ---------------------------------------------------------------- small graphs
 
 def _pairs(edges, n):
@@ -214,6 +238,9 @@ WORKLOADS = {
     "rmat-s22-ef16": Workload("rmat-s22-ef16", "rmat",
                               dict(scale=22, edge_factor=16, abc=(0.6, 0.2, 0.15), seed=22), (3, 6, 10)),
     "ba-4M-m8": Workload("ba-4M-m8", "ba", dict(n=4 * 1024 * 1024, m=8, seed=23), (3, 6, 10)),
+    # bipartite graph for butterfly counting: power-law degrees on both sides
+    "bip-cl-1M-16M": Workload("bip-cl-1M-16M", "bipartite",
+                              dict(nu=1 << 20, nv=1 << 18, gamma_u=2.5, gamma_v=2.2, pairs=16 << 20, seed=31)),
     # many small graphs of uneven sizes in one batched run (K per graph in 3..8)
     "chunglu-batch-4096": Workload("chunglu-batch-4096", "batch", dict(count=4096, seed=5, nmin=64, nmax=20000)),
 }
@@ -234,6 +261,12 @@ def workload_pairs(name: str):
     if w.kind == "ba":
         return barabasi_albert(p["n"], p["m"], p["seed"])
     raise KeyError(name)
+
+
+def bipartite_pairs(name: str):
+    """(nu, nv, u, v) for a named bipartite workload."""
+    p = WORKLOADS[name].params
+    return bipartite_chung_lu(p["nu"], p["nv"], p["gamma_u"], p["gamma_v"], p["pairs"], p["seed"])
 
 
 def batch_graphs(count: int = 4096, seed: int = 5, nmin: int = 64, nmax: int = 20000, threads: int = 16):
