@@ -1,14 +1,20 @@
 """Full-size GPU parity.
 
-* R-MAT scale 20 (15.7M edges), K = 3, 5, 8, 12: the GPU results must equal the
-  oracle's, compared through digests the oracle wrote (tests/golden/digests.json,
-  made by tests/golden/make_digests.py from oracle/ only).
-* R-MAT scale 23 + planted 600-clique (~112M edges), K = 3, 10, 50, 600: the
-  oracle cannot finish this size in a test, so the results are checked through
-  properties that hold at any size: for sampled surviving edges the support
-  equals the triangle count inside the returned truss and is >= K-2; K = 3
-  equals its closed form (survivors = edges in at least one triangle) on sampled
-  edges; the trusses are nested; the planted clique survives K = 600.
+Every full-size workload is compared bit for bit with the oracle through
+digests the oracle wrote (tests/golden/digests.json, made by
+tests/golden/make_digests.py from oracle/ only; mode P from the full graph for
+every K, hours of CPU time at scale 23):
+* R-MAT scale 20 (15.7M edges), K = 3, 5, 8, 12, under every schedule;
+* R-MAT scale 23 + planted 600-clique (111.4M edges), K = 3, 10, 50, 600,
+  under the hub, heuristic and learned schedules;
+* R-MAT scale 22 (61.6M edges) and Barabasi-Albert n = 4M, m = 8 (33.6M
+  edges), K = 3, 6, 10, under the plain, heuristic, learned and hub schedules;
+* the 4,096 Chung-Lu graphs of the batched workload (222M edges, K per graph)
+  in one batched run: per-graph pass counts, truss sizes and support sums, and
+  digests of every graph's mask and supports.
+The scale-23 graph is also checked through properties that hold at any size
+(sampled supports recounted inside the returned truss, the K = 3 closed form,
+nesting, the planted clique surviving K = 600).
 """
 import hashlib
 import json
@@ -55,23 +61,108 @@ def s20():
     return rp, col, n2o
 
 
-@pytest.mark.parametrize("schedule", [0, 1, 4, 5])
-def test_rmat20_digests(schedule, s20):
+def mlp_params():
+    from paper_2009_07929_amd import cost_model
+    params = cost_model.load_params("cuda")
+    assert params is not None, "the trained cost-model weights ship with the package"
+    return params
+
+
+def check_workload(name, csr, schedules, keyed_below=20_000_000):
+    """Runs every K of `name` under each schedule and compares with the golden
+    digests; the relabel-independent keyed digest is checked for trusses below
+    keyed_below edges (it sorts the survivors on the host)."""
     import torch
-    rp, col, n2o = s20
-    gold = GOLDEN["rmat-s20-ef16"]
+    rp, col, n2o = csr
+    gold = GOLDEN.get(name)
+    if gold is None:
+        pytest.skip("no golden digests for %s" % name)
     assert gold["m"] == len(col) and gold["n"] == len(rp) - 1
     g = kt().Graph(rp, col, device="cuda")
-    kt().ktruss_set_schedule(g, schedule)
-    for K in (3, 5, 8, 12):
-        print("case rmat-s20-ef16 K=%d schedule=%d" % (K, schedule), flush=True)
-        mask, sup, rounds = kt().ktruss_run(g, K)
-        torch.cuda.synchronize()
-        got = digests(rp, col, n2o, mask.cpu().numpy(), sup.cpu().numpy())
-        want = GOLDEN["rmat-s20-ef16"]["K"][str(K)]
-        assert rounds == want["rounds"], (K, rounds)
-        for key in ("truss_edges", "support_sum", "mask_sha256", "support_sha256", "keyed_sha256"):
-            assert got[key] == want[key], (K, key)
+    for schedule in schedules:
+        kt().ktruss_set_schedule(g, schedule, mlp_params() if schedule == 2 else None)
+        for Ks, want in sorted(gold["K"].items(), key=lambda kv: int(kv[0])):
+            K = int(Ks)
+            print("case %s K=%d schedule=%d" % (name, K, schedule), flush=True)
+            mask, sup, rounds = kt().ktruss_run(g, K)
+            torch.cuda.synchronize()
+            mask, sup = mask.cpu().numpy(), sup.cpu().numpy()
+            assert rounds == want["rounds"], (K, schedule, rounds, want["rounds"])
+            assert int(mask.sum()) == want["truss_edges"], (K, schedule)
+            assert int(sup.astype(np.int64).sum()) == want["support_sum"], (K, schedule)
+            assert hashlib.sha256(mask.tobytes()).hexdigest() == want["mask_sha256"], (K, schedule)
+            assert hashlib.sha256(np.ascontiguousarray(sup, "<i4").tobytes()).hexdigest() == \
+                want["support_sha256"], (K, schedule)
+            if want["truss_edges"] < keyed_below:
+                assert digests(rp, col, n2o, mask, sup)["keyed_sha256"] == want["keyed_sha256"], (K, schedule)
+    del g
+
+
+@pytest.mark.parametrize("schedule", [0, 1, 2, 3, 4, 5])
+def test_rmat20_digests(schedule, s20):
+    check_workload("rmat-s20-ef16", s20, [schedule])
+
+
+def built(name):
+    n, s, d = synth.workload_pairs(name)
+    return kt().ktruss_build_csr(s, d, n)
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_rmat23_clique_digests():
+    if "rmat-s23-ef16-clique600" not in GOLDEN:
+        pytest.skip("no golden digests for rmat-s23-ef16-clique600")
+    check_workload("rmat-s23-ef16-clique600", built("rmat-s23-ef16-clique600"), [4, 1, 2])
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("name", ["rmat-s22-ef16", "ba-4M-m8"])
+def test_evaluation_graph_digests(name):
+    if name not in GOLDEN:
+        pytest.skip("no golden digests for %s" % name)
+    check_workload(name, built(name), [0, 1, 2, 4])
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("schedule", ["autotuned", 4])
+def test_batch_digests(schedule):
+    """The whole batched workload in one ktruss_run_batched call."""
+    import torch
+    name = "chunglu-batch-4096"
+    gold = GOLDEN.get(name)
+    if gold is None:
+        pytest.skip("no golden digests for %s" % name)
+    p = synth.WORKLOADS[name].params
+    gs = synth.batch_graphs(p["count"], p["seed"], p["nmin"], p["nmax"])
+    K = np.array([x[3] for x in gs], np.int32)
+    assert K.tolist() == gold["K"]
+    csr = kt().build_csrs([(n, s, d) for n, s, d, _ in gs])
+    del gs
+    b = kt().Batch(csr, device="cuda", schedule=4 if schedule == 4 else 1)
+    if schedule == "autotuned":
+        from paper_2009_07929_amd import autotune
+        key = autotune.batch_class(b.G, b.m_total)
+        if key in autotune.load_cache():
+            autotune.apply(b, autotune.tuned_config(key))
+    print("case %s schedule=%s m=%d" % (name, schedule, b.m_total), flush=True)
+    mask, sup, rounds = kt().ktruss_run_batched(b, K)
+    torch.cuda.synchronize()
+    assert b.m_total == gold["m"]
+    mask, sup, rounds = mask.cpu().numpy(), sup.cpu().numpy(), rounds.cpu().numpy()
+    assert rounds.tolist() == gold["rounds"]
+    eo = b.edge_offsets()
+    hm, hs = hashlib.sha256(), hashlib.sha256()
+    for i in range(b.G):
+        mk, sg = mask[eo[i]:eo[i + 1]], np.ascontiguousarray(sup[eo[i]:eo[i + 1]], "<i4")
+        assert int(mk.sum()) == gold["truss_edges"][i], i
+        assert int(sg.astype(np.int64).sum()) == gold["support_sum"][i], i
+        hm.update(hashlib.sha256(mk.tobytes()).digest())
+        hs.update(hashlib.sha256(sg.tobytes()).digest())
+    assert hm.hexdigest() == gold["mask_sha256"]
+    assert hs.hexdigest() == gold["support_sha256"]
 
 
 def in_lists(n, col):
