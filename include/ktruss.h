@@ -53,8 +53,9 @@ extern "C" {
 #define KTRUSS_SCHED_PLAIN      0  /* every edge task on the thread-per-edge merge kernel */
 #define KTRUSS_SCHED_HEURISTIC  1  /* static degree heuristic bins rows/edges onto the kernel variants */
 #define KTRUSS_SCHED_LEARNED    2  /* MLP cost model bins rows/edges (falls back to HEURISTIC without weights) */
-#define KTRUSS_SCHED_FORCE_WAVE 3  /* every edge task on the wavefront-per-edge kernel (testing) */
-#define KTRUSS_SCHED_FORCE_HUB  4  /* every row on the workgroup-per-row kernel (testing) */
+#define KTRUSS_SCHED_FORCE_WAVE 3  /* every edge task on the wavefront-per-edge kernel (an ablation) */
+#define KTRUSS_SCHED_FORCE_HUB  4  /* every row kappa with tasks on the workgroup-per-hub-row kernel: the fastest
+                                      schedule on the large power-law graphs, the default of the benchmark */
 #define KTRUSS_SCHED_COARSE     5  /* one thread per row running its edge tasks in turn: the coarse granularity of
                                       Section III-A's Algorithm 2 (with Algorithm 3's updates of all three
                                       edges), kept as the ablation of the fine-grained path */
@@ -73,7 +74,13 @@ typedef struct ktruss_tuning {
                                 kappa; the row-kappa lengths sampled on edges 0, 16, 32, ... and weighted
                                 by 16) is at most this, ktruss_run/ktruss_support use thread-per-edge for
                                 every task and build no in-edge lists; 0: default 32, negative: never */
-    int32_t reserved[1];
+    int32_t incremental;     /* ktruss_run / ktruss_decompose: 0 recompute every pass's supports (Algorithm 1);
+                                1 after the first pass, keep the survivors' supports and take off each triangle a
+                                prune destroys (incremental maintenance); 2 as 1, except that a prune removing
+                                more than peel_ratio x the edges it keeps is followed by a recomputation.  Masks,
+                                supports and pass counts are the same in every mode.  Rounds replayed from a
+                                hipGraph (rounds_per_sync >= 2) use mode 1 for 2.  The batched form recomputes. */
+    int32_t peel_ratio;      /* incremental = 2: the ratio above (0: 1) */
 } ktruss_tuning;
 
 /* Cost model: 5 inputs -> 64 ReLU -> 64 ReLU -> 1 output, FP32.  Parameter
@@ -177,6 +184,7 @@ int32_t ktruss_prune(const ktruss_graph* g, int32_t K, const int32_t* support, u
 int32_t ktruss_run(const ktruss_graph* g, int32_t K, uint8_t* mask, int32_t* support,
                    int32_t* rounds, void* stream);
 
+
 /*
  * ktruss_decompose — the trussness of every edge (the K_max analysis of
  * Section IV, for all edges at once): the largest K whose K-truss holds the
@@ -240,6 +248,36 @@ int32_t ktruss_run_batched(const ktruss_batch* b, const int32_t* K, uint8_t* mas
 int32_t ktruss_set_schedule(ktruss_graph* g, int32_t mode, const float* mlp_params,
                             const ktruss_tuning* t);
 
+/* ------------------------------------------------------ butterfly counting */
+/*
+ * Butterflies of a bipartite graph: the paper's closing section (Section V)
+ * names butterfly counting, the 4-cycle motif of bipartite graphs, as a
+ * further problem for its fine-grained decomposition.  Sides U (nu vertices)
+ * and V (nv vertices); edges given as CSR rows over U: rowptr[nu+1] from 0 to
+ * m, columns in [0, nv) strictly ascending inside each row.  Edge e is the
+ * e-th non-zero.  A butterfly is u1 - v1 - u2 - v2 with u1 != u2, v1 != v2.
+ */
+typedef struct ktruss_bipartite {
+    int32_t nu, nv;
+    int64_t m;
+    const int32_t* rowptr;   /* device, nu+1 */
+    const int32_t* col;      /* device, m */
+    void* work;              /* device, >= ktruss_butterfly_workspace_bytes(nu, nv, m) bytes, 256-byte aligned */
+    int64_t work_bytes;
+} ktruss_bipartite;
+
+/* Workspace bytes of ktruss_butterflies (negative status on bad sizes). */
+int64_t ktruss_butterfly_workspace_bytes(int32_t nu, int32_t nv, int64_t m);
+/*
+ * count (device int64[m]): the butterflies containing each edge; total
+ * (host): the butterflies of the graph.  For two vertices of one side with w
+ * common neighbours, the pair spans C(w, 2) butterflies and each of its 2w
+ * edges lies in w - 1 of them; the sums are exact integers, identical from
+ * run to run.  E_INVALID for a malformed CSR (checked on the device before
+ * any counting), E_CAPACITY for a short workspace.  Synchronises `stream`.
+ */
+int32_t ktruss_butterflies(const ktruss_bipartite* g, int64_t* count, int64_t* total, void* stream);
+
 /* ------------------------------------------------------------- profiling */
 /*
  * Kernel timing, a measurement aid.  While enabled (on != 0), the support
@@ -265,6 +303,19 @@ int32_t ktruss_profile_enable(int32_t on);
  * Any out pointer may be NULL.  E_INVALID for a kind outside 0..5.
  */
 int32_t ktruss_profile_read(int32_t kind, int64_t* launches, double* total_ms, int64_t* tasks, int64_t* bytes);
+/*
+ * Statistics of the support passes profiled since the last enable, summed
+ * over the passes (Algorithm 3's tasks of each pass): out[0] alive edges
+ * (tasks), out[1] sum of their tail lengths |a12(j+1:)|, out[2] sum of their
+ * row-kappa lengths, out[3] sum of the supports (3 x triangles); for the
+ * tasks the workgroup-per-hub-row kernel ran: out[4] their count, out[5]
+ * their tail sum, out[6] their 64-bit hit words (sum of ceil(tail / 64)),
+ * out[7] the row-kappa elements it staged in LDS.  Writes min(len, 8)
+ * values (host int64).  The statistics live in a fixed device array of the
+ * library (no allocation) on the device current at ktruss_profile_enable;
+ * profiling on two devices at once is not supported.
+ */
+int32_t ktruss_profile_stats(int64_t* out, int32_t len);
 
 /* ------------------------------------------------------------- cost model */
 /*

@@ -87,7 +87,8 @@ FullLayout full_layout(int32_t n, int64_t m, int32_t G) {
     L.rs_hist = take(sizeof(int32_t) * (256 * (((size_t)m + kRsTile - 1) / kRsTile) + 1));
     L.is_hub = take((size_t)n + 1);
     L.hub_row = take((size_t)n + 1);
-    L.hitw = take(sizeof(unsigned long long) * kHitWords * (size_t)m);
+    L.hitw = take(sizeof(unsigned long long) * kHitWordsPerEdge * (size_t)m);
+    L.hwoff = take(sizeof(int64_t) * ((size_t)n + 1));
     L.wave_tasks = take(em);
     L.thread_tasks = take(em);
     L.ctl = take(sizeof(Ctl));
@@ -146,7 +147,8 @@ Work carve(void* work, int32_t n, int64_t m, int32_t G) {
     w.sc.is_hub = (uint8_t*)(base + L.is_hub);
     w.sc.hub_row = (uint8_t*)(base + L.hub_row);
     w.sc.hitw = (unsigned long long*)(base + L.hitw);
-    w.sc.hit_stride = m;
+    w.sc.hwoff = (int64_t*)(base + L.hwoff);
+    w.sc.hit_cap = (int64_t)kHitWordsPerEdge * m;
     w.sc.wave_tasks = (int32_t*)(base + L.wave_tasks);
     w.sc.thread_tasks = (int32_t*)(base + L.thread_tasks);
     w.ctl = (Ctl*)(base + L.ctl);
@@ -186,6 +188,8 @@ int32_t check_graph(const ktruss_graph* g, bool need_work) {
     if (!g->rowptr || (g->m > 0 && !g->col)) return fail(KTRUSS_E_INVALID, "graph rowptr/col is null");
     rc = check_schedule(g->schedule);
     if (rc != KTRUSS_OK) return rc;
+    if (g->tuning.incremental < 0 || g->tuning.incremental > 2 || g->tuning.peel_ratio < 0)
+        return fail(KTRUSS_E_INVALID, "tuning.incremental must be 0, 1 or 2 and peel_ratio >= 0");
     if (need_work) return check_work(g->work, g->work_bytes, (int64_t)full_layout(g->n, g->m, 0).L.total);
     return KTRUSS_OK;
 }
@@ -232,8 +236,13 @@ struct Profile {
     std::vector<hipEvent_t> pool;
     int64_t launches[kKinds] = {}, tasks[kKinds] = {}, bytes[kKinds] = {};
     double ms[kKinds] = {};
-    unsigned long long* work_dev = nullptr;  // device {merge-model work, support sum} of the profiled passes
+    unsigned long long* work_dev = nullptr;  // pass statistics (PassStat) on the device current at enable
 };
+
+// The pass statistics accumulate in a file-scope device array (one copy per
+// GPU) rather than in allocated memory; host code reaches it through the
+// address hipGetSymbolAddress reports for the current device.
+__device__ __align__(256) unsigned long long g_prof_stats[kPassStats];
 Profile& prof() {
     static Profile p;
     return p;
@@ -372,8 +381,10 @@ int32_t support_pass(int sched, int32_t n, const Work& w, int p, const PassDims&
     if (rc != KTRUSS_OK) return rc;
     rc = timer_end(tp, s);
     if (rc != KTRUSS_OK) return rc;
-    if (unsigned long long* acc = profile_work())
-        HIP_TRY(launch_pass_work(x, &w.ctl->m_buf[p], dm.m, w.ctl, acc, s), "pass work");
+    if (unsigned long long* acc = profile_work()) {
+        const bool hub = uses_csc(sched) && dm.items > 0;
+        HIP_TRY(launch_pass_work(x, &w.ctl->m_buf[p], dm.m, hub ? w.sc.hub_row : nullptr, acc, s), "pass work");
+    }
     return KTRUSS_OK;
 }
 
@@ -395,6 +406,7 @@ struct RunSpec {
     const int32_t* K;        // device int32[G] (batched form)
     int32_t* rounds_dev;     // device int32[G] (batched form)
     const float* mlp;        // cost-model parameters (LEARNED schedule)
+    int incremental;         // 0 recompute, 1 peel after every prune, 2 peel unless the prune removed too much
     // cost sampling (ktruss_collect_row_costs)
     bool collect;
     int32_t capacity;
@@ -412,7 +424,19 @@ RunSpec make_spec(int32_t n, int32_t m, const int32_t* rowptr, const int32_t* co
     r.sched = sched;
     r.tuning = t;
     r.mlp = mlp;
+    r.incremental = t.incremental;
     return r;
+}
+
+// In-edge lists: for the hub and binned schedules, and for the incremental
+// peel (the full neighbourhoods of a removed edge's ends).
+bool csc_needed(const RunSpec& r) { return uses_csc(r.sched) || r.incremental != 0; }
+
+PeelSpec peel_of(const RunSpec& r) {
+    PeelSpec pk{};
+    pk.on = r.incremental != 0;
+    pk.ratio = r.incremental == 2 ? (r.tuning.peel_ratio > 0 ? r.tuning.peel_ratio : 1) : 0;
+    return pk;
 }
 
 bool needs_features(const RunSpec& r) { return r.collect || (r.sched == KTRUSS_SCHED_LEARNED && r.mlp); }
@@ -429,7 +453,7 @@ int32_t prepare(const RunSpec& r, Work& w, int p, int32_t m_hint, hipStream_t s)
 // per-run row statistics of the cost model, the first preparation.
 int32_t set_up_run(const RunSpec& r, Work& w, hipStream_t s) {
     HIP_TRY(launch_init_run(w.b[0], r.rowptr, r.col, r.n, r.m, s), "init");
-    if (uses_csc(r.sched)) HIP_TRY(launch_build_csc(w.b[0], w.c[0], r.n, r.m, w.sc, s), "in-edge lists");
+    if (csc_needed(r)) HIP_TRY(launch_build_csc(w.b[0], w.c[0], r.n, r.m, w.sc, s), "in-edge lists");
     if (needs_features(r)) {
         HIP_TRY(launch_in_outdeg_sum(w.b[0], w.c[0], r.n, r.m, w.sc, s), "row statistics");
         hipError_t e = hipMemsetAsync(w.sc.cycles, 0, sizeof(unsigned long long) * ((size_t)r.n + 1), s);
@@ -438,21 +462,50 @@ int32_t set_up_run(const RunSpec& r, Work& w, hipStream_t s) {
     return KTRUSS_OK;
 }
 
-// Enqueues one prune round reading buffer p: support pass, per-graph status
-// (batched form), prune + compaction into buffer 1-p, preparation of the next
-// pass.  No host interaction: every kernel reads its counts from the control
-// block and does nothing once the fixpoint is reached.
-int32_t enqueue_round(const RunSpec& r, Work& w, int p, const PassDims& dm, hipStream_t s) {
-    int32_t rc = support_pass(r.sched, r.n, w, p, dm, s, r.collect ? w.sc.cycles : nullptr);
-    if (rc != KTRUSS_OK) return rc;
-    if (r.collect)
-        HIP_TRY(launch_append_costs(w.sc, r.n, r.capacity, r.out_x, r.out_y, w.ctl, s), "cost samples");
+// Enqueues one prune round reading buffer p: support pass (unless `pass` is
+// false: incremental maintenance kept buffer p's supports current), per-graph
+// status (batched form), prune + compaction into buffer 1-p (with the peel
+// when incremental), preparation of the next pass (recompute mode).  No host
+// interaction: every kernel reads its counts from the control block and does
+// nothing once the fixpoint is reached.
+int32_t enqueue_round(const RunSpec& r, Work& w, int p, const PassDims& dm, hipStream_t s, bool pass = true) {
+    if (pass) {
+        int32_t rc = support_pass(r.sched, r.n, w, p, dm, s, r.collect ? w.sc.cycles : nullptr);
+        if (rc != KTRUSS_OK) return rc;
+        if (r.collect)
+            HIP_TRY(launch_append_costs(w.sc, r.n, r.capacity, r.out_x, r.out_y, w.ctl, s), "cost samples");
+    }
     if (r.G > 0) HIP_TRY(launch_batch_status(w.b[p], w.batch, r.G, r.K, r.rounds_dev, w.ctl, s), "batch status");
-    const bool csc = uses_csc(r.sched);
+    const bool csc = csc_needed(r);
     HIP_TRY(launch_compact(w.b[p], w.b[1 - p], csc ? &w.c[p] : nullptr, csc ? &w.c[1 - p] : nullptr, r.n, 0, r.thr,
-                           nullptr, w.batch, w.sc, w.ctl, p, dm.m, r.m, s),
+                           nullptr, w.batch, w.sc, w.ctl, p, dm.m, r.m, peel_of(r), s),
             "prune launch");
-    return prepare(r, w, 1 - p, dm.m, s);
+    return r.incremental ? KTRUSS_OK : prepare(r, w, 1 - p, dm.m, s);
+}
+
+// Host-checked rounds from buffer p until the fixpoint.  ready: buffer p is
+// prepared for a support pass and h holds its dimensions; otherwise (the
+// incremental mode after a compaction) its supports are current, unless the
+// peel was skipped (h.need_support), when they are zeroed and recomputed.
+int32_t host_rounds(const RunSpec& r, Work& w, int p, int32_t m_hint, bool ready, Ctl& h, hipStream_t s) {
+    int32_t rc;
+    for (;;) {
+        if (!ready && h.need_support) {
+            HIP_TRY(launch_zero_support(w.b[p], w.ctl, p, m_hint, s), "zero supports");
+            rc = prepare(r, w, p, m_hint, s);
+            if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
+            if (rc != KTRUSS_OK) return rc;
+            ready = true;
+        }
+        const PassDims dm{m_hint, h.n_items, h.n_wave, h.n_thread};
+        rc = enqueue_round(r, w, p, dm, s, ready);
+        if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
+        if (rc != KTRUSS_OK) return rc;
+        if (h.done) return KTRUSS_OK;
+        m_hint = h.m_buf[1 - p];
+        p ^= 1;
+        ready = !r.incremental;  // recompute mode: enqueue_round prepared the next pass
+    }
 }
 
 // Per-thread private stream for graph capture (default priority).
@@ -467,29 +520,31 @@ hipStream_t capture_stream(hipError_t& e) {
 // round (set-up, in-edge lists, first preparation) is already enqueued on s.
 int32_t run_rounds(const RunSpec& r, Work& w, hipStream_t s, Ctl& h) {
     int32_t rc;
-    const bool csc = uses_csc(r.sched);
     h = Ctl{};
-    if (csc) {
+    if (uses_csc(r.sched)) {
         rc = read_ctl(w, h, s);
         if (rc != KTRUSS_OK) return rc;
     } else {
         h.m_buf[0] = r.m;
     }
     const int rps = r.tuning.rounds_per_sync;
+    if (rps <= 1) return host_rounds(r, w, 0, r.m, true, h, s);
     int p = 0;
     int32_t m_hint = r.m;
-    if (rps <= 1) {
-        for (;;) {
-            const PassDims dm{m_hint, h.n_items, h.n_wave, h.n_thread};
-            rc = enqueue_round(r, w, p, dm, s);
-            if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
-            if (rc != KTRUSS_OK) return rc;
-            if (h.done) return KTRUSS_OK;
-            m_hint = h.m_buf[1 - p];
-            p ^= 1;
-        }
+    RunSpec rg = r;
+    if (r.incremental) {
+        // the first pass computes the supports on the host loop; the captured
+        // rounds only prune and peel (always: a recomputation cannot be
+        // decided inside the graph)
+        const PassDims d1{m_hint, h.n_items, h.n_wave, h.n_thread};
+        rc = enqueue_round(r, w, 0, d1, s, true);
+        if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
+        if (rc != KTRUSS_OK || h.done) return rc;
+        m_hint = h.m_buf[1];
+        p = 1;
+        rg.incremental = 1;
     }
-    // hipGraph mode: two rounds (0 -> 1 -> 0) captured once with upper-bound
+    // hipGraph mode: two rounds (p -> 1-p -> p) captured once with upper-bound
     // grids, replayed ceil(rps / 2) times between host checks.
     hipError_t e;
     hipStream_t cs = capture_stream(e);
@@ -499,8 +554,8 @@ int32_t run_rounds(const RunSpec& r, Work& w, hipStream_t s, Ctl& h) {
     hipGraphExec_t exec = nullptr;
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
     t_capturing = true;
-    rc = enqueue_round(r, w, 0, dm, cs);
-    if (rc == KTRUSS_OK) rc = enqueue_round(r, w, 1, dm, cs);
+    rc = enqueue_round(rg, w, p, dm, cs, !rg.incremental);
+    if (rc == KTRUSS_OK) rc = enqueue_round(rg, w, 1 - p, dm, cs, !rg.incremental);
     t_capturing = false;
     hipError_t ec = hipStreamEndCapture(cs, &graph);
     if (rc != KTRUSS_OK) {
@@ -549,7 +604,7 @@ const char* ktruss_strerror(int32_t code) {
 
 const char* ktruss_last_error_message(void) { return t_msg; }
 int32_t ktruss_last_hip_error(void) { return t_hip; }
-int32_t ktruss_version(void) { return 200; }
+int32_t ktruss_version(void) { return 300; }
 
 int64_t ktruss_workspace_bytes(int32_t n, int64_t m, int32_t flags) {
     clear_error();
@@ -585,20 +640,16 @@ int32_t ktruss_profile_enable(int32_t on) {
         P.ms[k] = 0.0;
     }
     if (P.on) {
-        if (!P.work_dev) {
-            hipError_t e = hipMalloc((void**)&P.work_dev, 2 * sizeof(unsigned long long));
-            if (e != hipSuccess) {
-                P.work_dev = nullptr;
-                P.on = false;
-                return fail_hip(e, "profile accumulator");
-            }
-        }
-        hipError_t e = hipMemset(P.work_dev, 0, 2 * sizeof(unsigned long long));
+        void* acc = nullptr;
+        hipError_t e = hipGetSymbolAddress(&acc, HIP_SYMBOL(g_prof_stats));
+        if (e == hipSuccess) e = hipMemset(acc, 0, sizeof(unsigned long long) * kPassStats);
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) {
             P.on = false;
+            P.work_dev = nullptr;
             return fail_hip(e, "profile accumulator");
         }
+        P.work_dev = (unsigned long long*)acc;
     }
     return KTRUSS_OK;
 }
@@ -626,13 +677,27 @@ int32_t ktruss_profile_read(int32_t kind, int64_t* launches, double* total_ms, i
         if (kind == 0 && P.work_dev) {
             // merge-model algorithmic bytes of the profiled passes:
             // 4 (3 m + sum of tail and row-kappa lengths) reads + 8 (2 T + m) atomic read-writes
-            unsigned long long h[2] = {0, 0};
+            unsigned long long h[kPassStats] = {};
             hipError_t e = hipMemcpy(h, P.work_dev, sizeof(h), hipMemcpyDeviceToHost);
             if (e != hipSuccess) return fail_hip(e, "profile accumulator read");
-            const int64_t m = P.tasks[0], T = (int64_t)(h[1] / 3);
-            *bytes = 4 * (3 * m + (int64_t)h[0]) + 8 * (2 * T + m);
+            const int64_t m = (int64_t)h[kStatEdges], T = (int64_t)(h[kStatSupport] / 3);
+            *bytes = 4 * (3 * m + (int64_t)(h[kStatTail] + h[kStatRowK])) + 8 * (2 * T + m);
         }
     }
+    return KTRUSS_OK;
+}
+
+int32_t ktruss_profile_stats(int64_t* out, int32_t len) {
+    clear_error();
+    if (!out || len < 0) return fail(KTRUSS_E_INVALID, "out is null or len < 0");
+    Profile& P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    unsigned long long h[kPassStats] = {};
+    if (P.work_dev) {
+        hipError_t e = hipMemcpy(h, P.work_dev, sizeof(h), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return fail_hip(e, "profile accumulator read");
+    }
+    for (int32_t i = 0; i < len && i < kPassStats; ++i) out[i] = (int64_t)h[i];
     return KTRUSS_OK;
 }
 
@@ -675,7 +740,7 @@ int32_t ktruss_support(const ktruss_graph* g, const uint8_t* alive, int32_t* sup
     int p = 0;
     if (alive) {
         HIP_TRY(launch_compact(w.b[0], w.b[1], csc ? &w.c[0] : nullptr, csc ? &w.c[1] : nullptr, n, 1, 0, alive,
-                               w.batch, w.sc, w.ctl, 0, m, m, s),
+                               w.batch, w.sc, w.ctl, 0, m, m, PeelSpec{}, s),
                 "restrict to alive");
         p = 1;
         HIP_TRY(launch_set_final(w.ctl, 1, s), "final buffer");
@@ -774,24 +839,17 @@ int32_t ktruss_decompose(const ktruss_graph* g, int32_t* trussness, int32_t* k_m
         // threshold (their supports are exact), then rounds until the fixpoint
         r.thr = K - 1;
         HIP_TRY(launch_ctl_restart(w.ctl, s), "level restart");
-        const bool csc = uses_csc(r.sched);
+        const bool csc = csc_needed(r);
         HIP_TRY(launch_compact(w.b[f], w.b[1 - f], csc ? &w.c[f] : nullptr, csc ? &w.c[1 - f] : nullptr, r.n, 0, r.thr,
-                               nullptr, w.batch, w.sc, w.ctl, f, mf, r.m, s),
+                               nullptr, w.batch, w.sc, w.ctl, f, mf, r.m, peel_of(r), s),
                 "level prune");
-        rc = prepare(r, w, 1 - f, mf, s);
+        rc = r.incremental ? KTRUSS_OK : prepare(r, w, 1 - f, mf, s);
         if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
         if (rc != KTRUSS_OK) return rc;
-        int p = 1 - f;
-        int32_t m_hint = h.m_buf[p];
-        while (!h.done) {  // something was removed: recompute from buffer p
-            const PassDims dm{m_hint, h.n_items, h.n_wave, h.n_thread};
-            rc = enqueue_round(r, w, p, dm, s);
-            if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
-            if (rc != KTRUSS_OK) return rc;
-            if (h.done) break;
-            m_hint = h.m_buf[1 - p];
-            p ^= 1;
-        }
+        // something was removed: rounds from buffer 1-f (recomputed, or kept
+        // current by the peel) until the fixpoint
+        if (!h.done) rc = host_rounds(r, w, 1 - f, h.m_buf[1 - f], !r.incremental, h, s);
+        if (rc != KTRUSS_OK) return rc;
     }
     HIP_TRY(hipStreamSynchronize(s), "decompose sync");
     return KTRUSS_OK;
@@ -837,6 +895,7 @@ int32_t ktruss_run_batched(const ktruss_batch* b, const int32_t* K, uint8_t* mas
         return KTRUSS_OK;
     }
     RunSpec r = make_spec(n, m, b->rowptr, b->col, b->schedule, b->tuning, nullptr);
+    r.incremental = 0;  // graphs finishing inside a pass are written out by the compaction
     r.G = G;
     r.K = K;
     r.rounds_dev = rounds;
@@ -872,6 +931,7 @@ int32_t ktruss_collect_row_costs(const ktruss_graph* g, int32_t K, float* featur
     if (m == 0) return KTRUSS_OK;
     ktruss_tuning t = g->tuning;
     t.rounds_per_sync = 0;
+    t.incremental = 0;  // every pass is a timed support pass
     RunSpec r = make_spec(n, m, g->rowptr, g->col, KTRUSS_SCHED_FORCE_HUB, t, nullptr);
     r.thr = K - 2;
     r.collect = true;

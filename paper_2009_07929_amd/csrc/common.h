@@ -18,14 +18,17 @@ constexpr int kHubThreads = 256;     // 4 waves
 constexpr int kHubChunk = 256;       // tasks (in-edges of one row kappa) per hub item
 constexpr int kHubUnroll = 8;        // tail chunks whose loads a hub wave issues together
 constexpr int kHubBatch = 4;         // consecutive hub items per ticket of the persistent hub kernel
-constexpr int kSpanCap = 32768;      // widest label span staged as a rank bitmap
-constexpr int kSpanWords = kSpanCap / 32;
-constexpr int kKeyCap = 2 * kSpanWords;  // longest row kappa staged in LDS (keys / accumulators)
-constexpr int kHubMaxGrid = 256 * 8;     // persistent hub grid: 8 workgroups per CU
+// LDS of one hub workgroup: the rank bitmap (or the keys) and the accumulators
+// of row kappa, about 24.6 KB, so that the six workgroups per CU that the
+// kernel's register use allows all fit in the 160 KB of a CU.
+constexpr int kSpanWords = 1536;
+constexpr int kSpanCap = kSpanWords * 32;  // widest label span staged as a rank bitmap (49,152)
+constexpr int kKeyCap = 2 * kSpanWords;    // longest row kappa staged in LDS as keys (3,072)
+constexpr int kHubMaxGrid = 256 * 6;     // persistent hub grid: the 6 workgroups per CU that registers and LDS allow
 constexpr int kStreamMaxGrid = 256 * 16; // grid-stride cap of the thread/wave task kernels
 constexpr int kMlpGradMaxBlocks = 512;   // workgroups of the cost-model gradient kernel
 constexpr int kRsTile = 4096;            // (column, edge) pairs per workgroup of the radix-sort transpose
-constexpr int kHitWords = 8;             // 64-bit hit words per task: tail offsets below 512 (see k_support_hub)
+constexpr int kHitWordsPerEdge = 8;      // hit-word capacity of the workspace per edge (see hit_words_upto)
 
 // learned schedule defaults (predicted log2 shader cycles of a row's hub work)
 constexpr float kDefaultLearnedHubMin = 12.0f;
@@ -36,6 +39,15 @@ constexpr int kMinLearnedChunk = 16;     // fewest tasks per hub item
 // static degree heuristic defaults
 constexpr int kDefaultHubMinIn = 8;    // in-edges for a row kappa to be a hub row
 constexpr int kDefaultWaveMin = 192;   // merge length for wavefront-per-edge
+
+// Per-pass statistics gathered while profiling (ktruss_profile_stats): alive
+// edges, sum of their tail lengths, sum of their row-kappa lengths, sum of
+// supports (3 x triangles); for the tasks the hub kernel ran: their count,
+// tail sum and hit words, and the row-kappa elements it staged in LDS.
+enum PassStat {
+    kStatEdges = 0, kStatTail, kStatRowK, kStatSupport, kStatHubTasks, kStatHubTail, kStatHubWords,
+    kStatHubStaged, kPassStats
+};
 
 // Device-resident control block of one run.  Buffer b of the double-buffered
 // working graph holds m_buf[b] alive edges.
@@ -55,6 +67,8 @@ struct Ctl {
     int32_t csc_m;       // in-edge list entries (alive edges + tombstones of removed ones)
     int32_t csc_pack;    // the lists are being packed in this round (tombstones dominate)
     int32_t csc_next;    // entries after packing
+    int32_t need_support; // incremental maintenance skipped its peel: the next round recomputes supports
+    int32_t pad_;
     int64_t removed_total;
     unsigned long long merge_work;  // input's merge length summed over its edges (row tail + row kappa)
 };
@@ -110,8 +124,9 @@ struct Scratch {
     int32_t* rs_hist;     // int32[256 * ceil(m / kRsTile) + 1]: radix-sort digit histograms
     uint8_t* is_hub;      // uint8[n]
     uint8_t* hub_row;     // uint8[n]: row kappa has hub items in the current pass
-    unsigned long long* hitw;  // uint64[kHitWords * m]: hub hit words (hit_word_index)
-    int64_t hit_stride;        // edges of the workspace (m)
+    unsigned long long* hitw;  // uint64[hit_cap]: hub hit words, per row and task (hit_words_upto)
+    int64_t* hwoff;            // int64[n+1]: first hit word of every row's tasks in the current pass
+    int64_t hit_cap;           // words of hitw (kHitWordsPerEdge * m)
     int32_t* wave_tasks;  // int32[m]
     int32_t* thread_tasks;// int32[m]
 };
@@ -128,18 +143,26 @@ struct BatchCtx {
     int32_t* support;
 };
 
-// Hit word c of the task of edge e: word 0 of all tasks edge-major (read
-// 64 tasks at a time by the row-local sum), words 1.. of a task together
-// (written together by the hub kernel).
-__host__ __device__ inline int64_t hit_word_index(int32_t e, int32_t c, int64_t stride) {
-    return c == 0 ? (int64_t)e : stride + (int64_t)e * (kHitWords - 1) + (c - 1);
+// Hit words of the hub kernel.  A task whose tail has L elements owns
+// ceil(L / 64) consecutive 64-bit words, bit b of word c standing for tail
+// offset 64 c + b.  The tasks of a row (tails d-1, d-2, ..., 0 for a row of
+// d alive edges) own consecutive ranges, rows follow each other in label
+// order: hwoff[i] is the first word of row i and hwoff[i+1] its end, so the
+// task with tail L starts at hwoff[i+1] - hit_words_upto(L), where
+// hit_words_upto(x) = sum over L = 0..x of ceil(L / 64) = (q+1)(32q + r) for
+// x = 64q + r.  Words at or past the workspace's capacity do not exist: those
+// chunks add their hits directly.
+__host__ __device__ inline int64_t hit_words_upto(int32_t x) {
+    if (x <= 0) return 0;
+    const int64_t q = x >> 6, r = x & 63;
+    return (q + 1) * (32 * q + r);
 }
 
 struct Layout {
     size_t col[2], src[2], eid[2], S[2], rowptr[2];
     size_t cedge, csrc, ckey, cptr;
     size_t xscan, cxscan, blockcnt, blockoff, blockcnt2, blockoff2, alive_in, itemoff, items, ctail,
-        is_hub, hub_row, hitw, wave_tasks, thread_tasks, insum, cycles, act_off, act_list, feats, pred, chunk_sz,
+        is_hub, hub_row, hitw, hwoff, wave_tasks, thread_tasks, insum, cycles, act_off, act_list, feats, pred, chunk_sz,
         rs_hist;
     size_t ctl;        // Ctl
     size_t total;

@@ -79,6 +79,45 @@ __device__ __forceinline__ int block_sum(int v, int* s_wave) {
     return tot;
 }
 
+// 64-bit versions of the workgroup exclusive sum and total.
+template <int NT>
+__device__ __forceinline__ long long block_excl_sum64(long long v, long long* s_wave, long long& total) {
+    const int lane = __lane_id();
+    long long inc = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const long long u = __shfl_up(inc, o);
+        if (lane >= o) inc += u;
+    }
+    const int w = threadIdx.x >> 6;
+    if (lane == 63) s_wave[w] = inc;
+    __syncthreads();
+    long long wpre = 0, tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) {
+        const long long c = s_wave[i];
+        wpre += i < w ? c : 0;
+        tot += c;
+    }
+    __syncthreads();
+    total = tot;
+    return wpre + inc - v;
+}
+
+template <int NT>
+__device__ __forceinline__ long long block_sum64(long long v, long long* s_wave) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int w = threadIdx.x >> 6;
+    if (__lane_id() == 0) s_wave[w] = v;
+    __syncthreads();
+    long long tot = 0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) tot += s_wave[i];
+    __syncthreads();
+    return tot;
+}
+
 static inline unsigned grid_for(int64_t items, int per_block = kBlock) {
     int64_t g = (items + per_block - 1) / per_block;
     return (unsigned)(g < 1 ? 1 : g);

@@ -1,0 +1,137 @@
+// Incremental support maintenance: the decrement form of Algorithm 1's
+// recompute line (Section II-A).  After a prune, the survivors keep their
+// supports (the compaction copies them) and every triangle of the round's
+// alive graph that loses at least one edge is charged exactly once, by its
+// removed edge with the smallest position: each of the triangle's surviving
+// edges loses one support.  A survivor's support then equals the number of
+// triangles it still closes, which is what a recomputation on the new alive
+// graph would give, so the fixpoint, the supports and the pass count are
+// those of the recompute loop.
+//
+// The task of removed edge f = (u, v), u < v, lists every triangle (u, v, w)
+// of the round's alive graph from the full neighbourhoods of u and v: the
+// out-row of a vertex holds its larger neighbours, its in-edge list (the
+// transpose, entries ordered by row) its smaller ones, both ascending.  The
+// third vertex w lies below u (in-list of u against in-list of v), between u
+// and v (out-row of u before f against in-list of v) or above v (out-row of
+// u after f, Algorithm 3's tail, against out-row of v).  One wave per removed
+// edge: the lanes walk the shorter list of each pair and binary-search the
+// longer one.
+#include "device_util.h"
+#include "kernels.h"
+
+namespace kt {
+
+namespace {
+
+// Every common value of two ascending lists A = [a0, a1) and B = [b0, b1),
+// given by value and edge accessors, is passed to hit(edge in A, edge in B).
+// The lanes walk the shorter list and binary-search the longer.
+template <class VA, class EA, class VB, class EB, class H>
+__device__ __forceinline__ void wave_common(int32_t a0, int32_t a1, VA va, EA ea, int32_t b0, int32_t b1, VB vb,
+                                            EB eb, H hit) {
+    if (a0 >= a1 || b0 >= b1) return;
+    const int lane = __lane_id();
+    const bool walk_a = a1 - a0 <= b1 - b0;
+    const int32_t w0 = walk_a ? a0 : b0, w1 = walk_a ? a1 : b1;
+    const int32_t s0 = walk_a ? b0 : a0, s1 = walk_a ? b1 : a1;
+    for (int32_t base = w0; base < w1; base += 64) {
+        const int32_t q = base + lane;
+        if (q >= w1) continue;
+        const int32_t val = walk_a ? va(q) : vb(q);
+        int32_t lo = s0, len = s1 - s0;
+        while (len > 0) {
+            const int32_t half = len >> 1;
+            const int32_t y = walk_a ? vb(lo + half) : va(lo + half);
+            if (y < val) {
+                lo += half + 1;
+                len -= half + 1;
+            } else {
+                len = half;
+            }
+        }
+        if (lo < s1 && (walk_a ? vb(lo) : va(lo)) == val) {
+            if (walk_a) hit(ea(q), eb(lo));
+            else hit(ea(lo), eb(q));
+        }
+    }
+}
+
+// First entry of in-edge list [c0, c1) whose row is >= r.
+__device__ __forceinline__ int32_t in_lower(const int32_t* __restrict__ csrc, int32_t c0, int32_t c1, int32_t r) {
+    return c0 + lower_bound_i32(csrc + c0, c1 - c0, r);
+}
+
+__global__ __launch_bounds__(kBlock) void k_peel(Buf x, Buf y, Csc c, const int32_t* __restrict__ xscan,
+                                               const int32_t* __restrict__ frontier, Ctl* ctl, int p,
+                                               int32_t ratio) {
+    if (ctl->done) return;
+    const int32_t nf = ctl->m_buf[p] - ctl->kept;  // edges removed by this prune
+    // auto mode: a frontier larger than ratio x the survivors is left to a
+    // recomputation (the next round runs a support pass instead)
+    if (ratio > 0 && (int64_t)nf > (int64_t)ratio * ctl->kept) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctl->need_support = 1;
+        return;
+    }
+    const int32_t* __restrict__ col = x.col;
+    const int32_t* __restrict__ csrc = c.src;
+    const int32_t* __restrict__ cedge = c.edge;
+    const int32_t nw = (int32_t)(gridDim.x * (kBlock / 64));
+    for (int32_t wid = (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 6); wid < nf; wid += nw) {
+        const int32_t f = frontier[wid];
+        const int32_t u = x.src[f], v = col[f];
+        // charge the triangle (f, e1, e2) here unless a removed edge with a
+        // smaller position is in it; decrement its surviving edges
+        auto charge = [&](int32_t e1, int32_t e2) {
+            if (e1 < 0 || e2 < 0) return;  // an edge removed in an earlier round: not a triangle of this round
+            const int32_t q1 = xscan[e1], q2 = xscan[e2];
+            if ((q1 < 0 && e1 < f) || (q2 < 0 && e2 < f)) return;
+            if (q1 >= 0) atomicSub(&y.S[q1], 1);
+            if (q2 >= 0) atomicSub(&y.S[q2], 1);
+        };
+        const int32_t ru0 = x.rowptr[u], ru1 = x.rowptr[u + 1];
+        const int32_t rv0 = x.rowptr[v], rv1 = x.rowptr[v + 1];
+        const int32_t cu0 = c.ptr[u], cu1 = c.ptr[u + 1];
+        const int32_t cv0 = c.ptr[v], cv1 = c.ptr[v + 1];
+        const int32_t cvu = in_lower(csrc, cv0, cv1, u);  // in(v) entries of rows < u end here; f's entry follows
+        auto in_val = [&](int32_t q) { return csrc[q]; };
+        auto in_edge = [&](int32_t q) { return cedge[q]; };
+        auto row_val = [&](int32_t q) { return col[q]; };
+        auto row_edge = [&](int32_t q) { return q; };
+        // w < u: edges (w, u) and (w, v)
+        wave_common(cu0, cu1, in_val, in_edge, cv0, cvu, in_val, in_edge, charge);
+        // u < w < v: edges (u, w) and (w, v)
+        wave_common(ru0, f, row_val, row_edge, min(cvu + 1, cv1), cv1, in_val, in_edge, charge);
+        // w > v: edges (u, w) and (v, w)
+        wave_common(f + 1, ru1, row_val, row_edge, rv0, rv1, row_val, row_edge, charge);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_support(Buf x, const Ctl* __restrict__ ctl, int p) {
+    const int32_t m = ctl->m_buf[p];
+    for (int32_t e = (int32_t)(blockIdx.x * kBlock + threadIdx.x); e < m; e += (int32_t)(gridDim.x * kBlock))
+        x.S[e] = 0;
+}
+
+__global__ void k_need_support_clear(Ctl* ctl) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->need_support = 0;
+}
+
+}  // namespace
+
+hipError_t launch_peel(const Buf& x, const Buf& y, const Csc& c, const int32_t* xscan, const int32_t* frontier,
+                       Ctl* ctl, int p, int32_t ratio, int32_t m_hint, hipStream_t s) {
+    if (m_hint <= 0) return hipSuccess;
+    k_need_support_clear<<<1, 64, 0, s>>>(ctl);
+    const unsigned grid = min(grid_for((int64_t)m_hint * 64), (unsigned)kStreamMaxGrid);
+    k_peel<<<grid, kBlock, 0, s>>>(x, y, c, xscan, frontier, ctl, p, ratio);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_support(const Buf& x, const Ctl* ctl, int p, int32_t m_hint, hipStream_t s) {
+    if (m_hint <= 0) return hipSuccess;
+    k_zero_support<<<min(grid_for(m_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, ctl, p);
+    return hipGetLastError();
+}
+
+}  // namespace kt

@@ -111,6 +111,84 @@ void device_scan(const F& f, int32_t N, const Ctl* ctl, Scratch& sc, int32_t* ou
     k_scan_write<F><<<G, kBlock, 0, s>>>(f, N, ctl, sc.blockoff, out, total_dst);
 }
 
+// ---- the same scan in 64 bits (hit-word offsets), out[N] = total
+
+template <class F>
+__global__ __launch_bounds__(kBlock) void k_scan64_partial(F f, int32_t N, const Ctl* __restrict__ ctl,
+                                                         long long* __restrict__ blockcnt) {
+    __shared__ long long s_wave[kBlock / 64];
+    if (ctl && ctl->done) return;
+    int32_t lo, hi;
+    span_of(N, lo, hi);
+    long long c = 0;
+    for (int32_t i = lo + (int32_t)threadIdx.x; i < hi; i += kBlock) c += f(i);
+    c = block_sum64<kBlock>(c, s_wave);
+    if (threadIdx.x == 0) blockcnt[blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan64_blocks(const long long* __restrict__ blockcnt,
+                                                              long long* __restrict__ blockoff, int32_t G,
+                                                              const Ctl* __restrict__ ctl) {
+    __shared__ long long s_wave[kScanThreads / 64];
+    if (ctl && ctl->done) return;
+    constexpr int PER = kMaxScanBlocks / kScanThreads;
+    const int t = threadIdx.x;
+    long long v[PER];
+    long long local = 0;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int idx = t * PER + j;
+        v[j] = idx < G ? blockcnt[idx] : 0;
+        local += v[j];
+    }
+    long long total;
+    long long run = block_excl_sum64<kScanThreads>(local, s_wave, total);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int idx = t * PER + j;
+        if (idx < G) blockoff[idx] = run;
+        run += v[j];
+    }
+}
+
+template <class F>
+__global__ __launch_bounds__(kBlock) void k_scan64_write(F f, int32_t N, const Ctl* __restrict__ ctl,
+                                                       const long long* __restrict__ blockoff,
+                                                       int64_t* __restrict__ out) {
+    __shared__ long long s_wave[kBlock / 64];
+    if (ctl && ctl->done) return;
+    int32_t lo, hi;
+    span_of(N, lo, hi);
+    long long base = blockoff[blockIdx.x];
+    for (int32_t t0 = lo; t0 < hi; t0 += kBlock) {
+        const int32_t i = t0 + (int32_t)threadIdx.x;
+        const long long v = i < hi ? f(i) : 0;
+        long long tot;
+        const long long pre = block_excl_sum64<kBlock>(v, s_wave, tot);
+        if (i < hi) out[i] = base + pre;
+        base += tot;
+    }
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[N] = base;
+}
+
+// The per-workgroup partials live in the paired count / offset scratch
+// (2 * kMaxScanBlocks int32 each, 256-byte aligned).
+template <class F>
+void device_scan64(const F& f, int32_t N, const Ctl* ctl, Scratch& sc, int64_t* out, hipStream_t s) {
+    const int32_t G = scan_grid(N);
+    long long* cnt = reinterpret_cast<long long*>(sc.blockcnt2);
+    long long* off = reinterpret_cast<long long*>(sc.blockoff2);
+    k_scan64_partial<F><<<G, kBlock, 0, s>>>(f, N, ctl, cnt);
+    k_scan64_blocks<<<1, kScanThreads, 0, s>>>(cnt, off, G, ctl);
+    k_scan64_write<F><<<G, kBlock, 0, s>>>(f, N, ctl, off, out);
+}
+
+// Hit words of the tasks of row i (tails d-1 .. 0).
+struct RowWords {
+    const int32_t* rowptr;
+    __device__ long long operator()(int32_t i) const { return hit_words_upto(rowptr[i + 1] - rowptr[i] - 1); }
+};
+
 // ---- in-edge lists by a stable LSD radix sort of (column, edge) pairs
 //
 // 8-bit digits.  Per pass: every workgroup histograms the digits of its tile
@@ -199,18 +277,14 @@ __global__ __launch_bounds__(kBlock) void k_csc_rows(const int32_t* __restrict__
 }
 
 // Tail length of the task of every in-edge list entry of the pass: the part
-// of row i after the edge (Algorithm 3's a12(j+1:)); 0 for a tombstone.  Also
-// clears the first hit word of every alive edge, so that tasks the hub kernel
-// does not run read as having no hits.
-__global__ __launch_bounds__(kBlock) void k_task_tails(Buf x, Csc c, const Ctl* __restrict__ ctl, int p,
-                                                     int32_t* __restrict__ ctail,
-                                                     unsigned long long* __restrict__ hitw) {
+// of row i after the edge (Algorithm 3's a12(j+1:)); 0 for a tombstone.
+__global__ __launch_bounds__(kBlock) void k_task_tails(Buf x, Csc c, const Ctl* __restrict__ ctl,
+                                                     int32_t* __restrict__ ctail) {
     if (ctl->done) return;
-    const int32_t nc = ctl->csc_m, m = ctl->m_buf[p];
+    const int32_t nc = ctl->csc_m;
     for (int32_t q = (int32_t)(blockIdx.x * kBlock + threadIdx.x); q < nc; q += (int32_t)(gridDim.x * kBlock)) {
         const int32_t e = c.edge[q];
         ctail[q] = e < 0 ? 0 : x.rowptr[c.src[q] + 1] - e - 1;
-        if (q < m) hitw[hit_word_index(q, 0, 0)] = 0ull;
     }
 }
 
@@ -507,12 +581,17 @@ __global__ __launch_bounds__(kBlock) void k_task_scatter(TaskClass tc, const Ctl
 
 }  // namespace
 
-// In-edge lists of buffer b by the stable radix sort above: edges sorted by
-// column, positions in ascending order within a column.
-hipError_t launch_build_csc(const Buf& b, const Csc& c, int32_t n, int32_t m, Scratch& sc, hipStream_t s) {
+// Stable transpose of CSR columns by the radix sort above (8-bit digits,
+// as many passes as n's bits need): keys_out gets the columns in ascending
+// order, vals_out the position holding each (ascending within a column), and
+// ptr[k] (k in [0, n]) the first entry with a column >= k.  tk, tv: two
+// int32[m] ping-pong buffers each, distinct from the outputs; uses
+// sc.rs_hist, sc.blockcnt and sc.blockoff.
+hipError_t launch_radix_transpose(const int32_t* keys, int32_t m, int32_t n, int32_t* keys_out, int32_t* vals_out,
+                                  int32_t* ptr, int32_t* const tk[2], int32_t* const tv[2], Scratch& sc,
+                                  hipStream_t s) {
     if (m == 0) {
-        k_fill_i32<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(c.ptr, n + 1, 0);
-        k_fill_i32<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(sc.alive_in, n + 1, 0);
+        k_fill_i32<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(ptr, n + 1, 0);
         return hipGetLastError();
     }
     int bits = 0;
@@ -520,23 +599,75 @@ hipError_t launch_build_csc(const Buf& b, const Csc& c, int32_t n, int32_t m, Sc
     const int passes = bits <= 8 ? 1 : (bits + 7) / 8;
     const int32_t nblk = (int32_t)(((int64_t)m + kRsTile - 1) / kRsTile);
     const int32_t nh = 256 * nblk;
-    int32_t* kbuf[2] = {sc.xscan, sc.wave_tasks};
-    int32_t* vbuf[2] = {sc.cxscan, sc.thread_tasks};
-    const int32_t* kin = b.col;
+    const int32_t* kin = keys;
     const int32_t* vin = nullptr;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
-        int32_t* kout = p == passes - 1 ? c.key : kbuf[p & 1];
-        int32_t* vout = p == passes - 1 ? c.edge : vbuf[p & 1];
+        int32_t* kout = p == passes - 1 ? keys_out : tk[p & 1];
+        int32_t* vout = p == passes - 1 ? vals_out : tv[p & 1];
         k_rs_hist<<<nblk, kBlock, 0, s>>>(kin, m, shift, nblk, sc.rs_hist);
         device_scan(FromArray{sc.rs_hist}, nh, nullptr, sc, sc.rs_hist, nullptr, s);
         k_rs_scatter<<<nblk, kBlock, 0, s>>>(kin, vin, m, shift, nblk, sc.rs_hist, kout, vout);
         kin = kout;
         vin = vout;
     }
-    k_col_ptr<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(kin, m, n, c.ptr);
+    k_col_ptr<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(kin, m, n, ptr);
+    return hipGetLastError();
+}
+
+// In-edge lists of buffer b: the transpose of its columns; every entry's row.
+hipError_t launch_build_csc(const Buf& b, const Csc& c, int32_t n, int32_t m, Scratch& sc, hipStream_t s) {
+    if (m == 0) {
+        k_fill_i32<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(c.ptr, n + 1, 0);
+        k_fill_i32<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(sc.alive_in, n + 1, 0);
+        return hipGetLastError();
+    }
+    int32_t* const tk[2] = {sc.xscan, sc.wave_tasks};
+    int32_t* const tv[2] = {sc.cxscan, sc.thread_tasks};
+    hipError_t e = launch_radix_transpose(b.col, m, n, c.key, c.edge, c.ptr, tk, tv, sc, s);
+    if (e != hipSuccess) return e;
     k_csc_rows<<<grid_for(m), kBlock, 0, s>>>(b.src, c.edge, m, c.src);
     k_alive_in_init<<<grid_for(n), kBlock, 0, s>>>(c.ptr, n, sc.alive_in);
+    return hipGetLastError();
+}
+
+// Row (last r with rowptr[r] <= e) of the positions pos[0 .. m).
+__global__ __launch_bounds__(kBlock) void k_rows_of(const int32_t* __restrict__ rowptr, int32_t nrows,
+                                                  const int32_t* __restrict__ pos, int32_t m,
+                                                  int32_t* __restrict__ out) {
+    const int64_t j = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (j >= m) return;
+    const int32_t e = pos[j];
+    int32_t lo = 0, hi = nrows;
+    while (hi - lo > 1) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (rowptr[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    out[j] = lo;
+}
+
+hipError_t launch_rows_of(const int32_t* rowptr, int32_t nrows, const int32_t* pos, int32_t m, int32_t* out,
+                          hipStream_t s) {
+    if (m <= 0) return hipSuccess;
+    k_rows_of<<<grid_for(m), kBlock, 0, s>>>(rowptr, nrows, pos, m, out);
+    return hipGetLastError();
+}
+
+// Butterfly tasks of pair vertex p: none without wedges, one when its W(p)
+// wedges fit the hash, else one per window of labels.
+struct BfTasks {
+    const int64_t* W;
+    int64_t hash_max, nwin;
+    __device__ long long operator()(int32_t p) const {
+        const int64_t w = W[p];
+        return w == 0 ? 0 : (w <= hash_max ? 1 : nwin);
+    }
+};
+
+hipError_t launch_bf_task_offsets(const int64_t* W, int32_t nP, int64_t hash_max, int64_t nwin, int64_t* off,
+                                  Scratch& sc, hipStream_t s) {
+    device_scan64(BfTasks{W, hash_max, nwin}, nP, nullptr, sc, off, s);
     return hipGetLastError();
 }
 
@@ -562,7 +693,9 @@ hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched,
     const bool learned = sched == KTRUSS_SCHED_LEARNED && mlp;
     // task tails (the in-edge lists hold tombstones of removed edges)
     if (m_hint > 0)
-        k_task_tails<<<min(grid_for(m0), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, c, ctl, p, sc.ctail, sc.hitw);
+        k_task_tails<<<min(grid_for(m0), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, c, ctl, sc.ctail);
+    // first hit word of every row's tasks (a 64-bit scan of the rows' word counts)
+    device_scan64(RowWords{x.rowptr}, n, ctl, sc, sc.hwoff, s);
     if (sched == KTRUSS_SCHED_HEURISTIC || (sched == KTRUSS_SCHED_LEARNED && !mlp)) {
         const int32_t hub_min_in = t.hub_min_work > 0 ? t.hub_min_work : kDefaultHubMinIn;
         k_heuristic_bins<<<grid_for(n), kBlock, 0, s>>>(x.rowptr, sc.alive_in, n, hub_min_in, sc.is_hub, ctl);

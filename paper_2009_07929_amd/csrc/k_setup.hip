@@ -11,6 +11,7 @@ __global__ void k_ctl_reset(Ctl* ctl, int32_t m) {
         ctl->m_buf[0] = m;
         ctl->m_buf[1] = 0;
         ctl->done = 0;
+        ctl->need_support = 0;
         ctl->final_buf = 0;
         ctl->rounds = 0;
         ctl->err = 0;
@@ -116,7 +117,10 @@ __global__ __launch_bounds__(kBlock) void k_fill_value(int32_t* __restrict__ a, 
 // Next decomposition level: the fixpoint flag is cleared so that the rounds
 // continue from the final buffer.
 __global__ void k_ctl_restart(Ctl* ctl) {
-    if (threadIdx.x == 0) ctl->done = 0;
+    if (threadIdx.x == 0) {
+        ctl->done = 0;
+        ctl->need_support = 0;
+    }
 }
 
 __global__ void k_set_final(Ctl* ctl, int f) {

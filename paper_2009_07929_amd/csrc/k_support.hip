@@ -134,10 +134,12 @@ static_assert(64 % kHubUnroll == 0, "a step's chunk indices jj + u stay within t
 // one atomic per task.  In the bitmap case a label beyond row kappa is
 // clamped onto a zero guard word, so a lookup needs no compare-and-select.
 template <int MODE>
-__device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __restrict__ hitw, int64_t hit_stride,
-                                          const int32_t* __restrict__ cedge, const int32_t* __restrict__ ctail,
-                                          int32_t c0, int32_t ntask, int32_t k, int32_t rs, int32_t d, int32_t last,
-                                          uint32_t guard, const uint2* s_bm, int32_t* s_acc) {
+__device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __restrict__ hitw,
+                                          const int64_t* __restrict__ hwoff, int64_t hit_cap,
+                                          const int32_t* __restrict__ cedge, const int32_t* __restrict__ csrc,
+                                          const int32_t* __restrict__ ctail, int32_t c0, int32_t ntask, int32_t k,
+                                          int32_t rs, int32_t d, int32_t last, uint32_t guard, const uint2* s_bm,
+                                          int32_t* s_acc) {
     const int32_t* __restrict__ col = x.col;
     const int32_t* s_keys = reinterpret_cast<const int32_t*>(s_bm);
     const unsigned long long* s_bm64 = reinterpret_cast<const unsigned long long*>(s_bm);
@@ -146,9 +148,11 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
     constexpr int kWaves = kHubThreads / 64;
     const int32_t mine = wv + kWaves * lane;
     int32_t t_e = 0, t_L = 0;
+    int64_t t_w = 0;  // first hit word of task r
     if (mine < ntask) {
         t_e = cedge[c0 + mine];
         t_L = ctail[c0 + mine];
+        if (t_L > 0) t_w = hwoff[csrc[c0 + mine] + 1] - hit_words_upto(t_L);
     }
     const int32_t t_nc = (t_L + 63) >> 6;          // chunks of task r
     const int32_t t_P = wave_incl_scan(t_nc);       // chunks of tasks 0..r
@@ -169,7 +173,9 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
         const int32_t dc = dv ? j - dS : 0;                   // chunk index within the task
         const int32_t dbase = dv ? de + 1 + 64 * dc : 0;      // first tail position of the chunk
         const int32_t dlen = dv ? min(64, dL - 64 * dc) : 0;  // elements in the chunk
-        const unsigned long long far = __ballot(dv && dc >= kHitWords);  // chunks whose hits add directly
+        const int64_t dw = __shfl(t_w, lo) + dc;               // the chunk's hit word
+        const bool dfar = dv && dw >= hit_cap;                  // beyond the capacity: hits add directly
+        const unsigned long long far = __ballot(dfar);
         const int32_t nch = min(64, C - b0);
         uint32_t word_lo = 0, word_hi = 0;
         for (int32_t jj = 0; jj < nch; jj += kHubUnroll) {
@@ -239,7 +245,7 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
                     word_hi = (uint32_t)(hb[u] >> 32);
                 }
             }
-            // S(i, w) of chunks past kHitWords (tails longer than 64 * kHitWords)
+            // S(i, w) of chunks without a hit word
             if (far) {
 #pragma unroll
                 for (int u = 0; u < kHubUnroll; ++u)
@@ -250,7 +256,7 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
         // block end: lane j writes chunk j's hit word and adds its hits to S(i, kappa)
         const unsigned long long word = ((unsigned long long)word_hi << 32) | word_lo;
         // written once and read once by k_hit_sum: a streaming store keeps L2 for the tails
-        if (dv && dc < kHitWords) __builtin_nontemporal_store(word, &hitw[hit_word_index(de, dc, hit_stride)]);
+        if (dv && !dfar) __builtin_nontemporal_store(word, &hitw[dw]);
         // S(i, kappa): the block's chunks of one task sit on consecutive lanes; a
         // segmented sum gives one atomic per task and block instead of one per chunk
         const int32_t key = dv ? de : -1;
@@ -268,7 +274,8 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
 
 __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const HubItem* __restrict__ items,
                                                            const int32_t* __restrict__ ctail, Ctl* ctl,
-                                                           unsigned long long* __restrict__ hitw, int64_t hit_stride,
+                                                           unsigned long long* __restrict__ hitw,
+                                                           const int64_t* __restrict__ hwoff, int64_t hit_cap,
                                                            unsigned long long* __restrict__ cycles) {
     __shared__ uint2 s_bm[kSpanWords + 1];  // rank bitmap {bits, set bits before this word} + a zero guard word; or keys
     __shared__ int32_t s_acc[kKeyCap];
@@ -348,14 +355,14 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
                 __syncthreads();
             }
             if (cur_mode == kModeBitmap)
-                hub_tasks<kModeBitmap>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, cur_rs, cur_d, cur_last, cur_guard,
-                                       s_bm, s_acc);
+                hub_tasks<kModeBitmap>(x, hitw, hwoff, hit_cap, c.edge, c.src, ctail, c0, ntask, k, cur_rs, cur_d, cur_last,
+                                   cur_guard, s_bm, s_acc);
             else if (cur_mode == kModeKeys)
-                hub_tasks<kModeKeys>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, cur_rs, cur_d, cur_last, cur_guard,
-                                     s_bm, s_acc);
+                hub_tasks<kModeKeys>(x, hitw, hwoff, hit_cap, c.edge, c.src, ctail, c0, ntask, k, cur_rs, cur_d, cur_last,
+                                   cur_guard, s_bm, s_acc);
             else
-                hub_tasks<kModeGlobal>(x, hitw, hit_stride, c.edge, ctail, c0, ntask, k, cur_rs, cur_d, cur_last, cur_guard,
-                                       s_bm, s_acc);
+                hub_tasks<kModeGlobal>(x, hitw, hwoff, hit_cap, c.edge, c.src, ctail, c0, ntask, k, cur_rs, cur_d, cur_last,
+                                   cur_guard, s_bm, s_acc);
             if (cycles) {  // per-row cost samples for the cost model (shader clock)
                 __syncthreads();
                 if (t == 0) atomicAdd(&cycles[k], (unsigned long long)clock64() - t_start);
@@ -390,15 +397,17 @@ __device__ __forceinline__ unsigned long long transpose64(unsigned long long v, 
 // position p of row i gains one for every earlier task j of row i (a hub task:
 // hub_row[col[j]]) whose hit words have the bit of tail offset p - j - 1.
 // One wave per window of 64 positions P0 .. P0+63.  Lane l takes the task at
-// P0 + l and shifts its first word (cleared for tasks the hub kernel did not
-// run) so that bit l' stands for position P0 + l'; a 64x64 bit transpose and a
-// popcount then give every position the hits of the window's own tasks (a task
-// has no hits past its row, so tasks of other rows add nothing).  The only earlier tasks that reach into the window are
-// those of the row holding P0 when it starts before P0: their words are
+// P0 + l and shifts its first word so that bit l' stands for position
+// P0 + l'; a 64x64 bit transpose and a popcount then give every position the
+// hits of the window's own tasks (a task has no hits past its row, so tasks of
+// other rows add nothing).  The only earlier tasks that reach into the window
+// are those of the row holding P0 when it starts before P0: their words are
 // aligned to the window with a funnel shift of two words and summed the same
-// way, 64 tasks at a time, from at most 64 * kHitWords positions back.
+// way, 64 tasks at a time, back to the start of the row.  A word at or past
+// the capacity was never written: its chunk added its hits directly.
 __global__ __launch_bounds__(kBlock) void k_hit_sum(Buf x, const unsigned long long* __restrict__ hitw,
-                                                  int64_t stride, const uint8_t* __restrict__ hub_row,
+                                                  const int64_t* __restrict__ hwoff, int64_t hit_cap,
+                                                  const uint8_t* __restrict__ hub_row,
                                                   const int32_t* __restrict__ count, const Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     const int32_t m = *count;
@@ -408,73 +417,83 @@ __global__ __launch_bounds__(kBlock) void k_hit_sum(Buf x, const unsigned long l
     const int32_t P0 = (int32_t)P0l;
     const int32_t* __restrict__ col = x.col;
     const int32_t p = P0 + lane;
-    const bool in = p < m;
-    // word 0 of every task: cleared by the pass preparation, written by the
-    // hub kernel for its tasks; position P0 + lane + 1 is tail offset 0 of task p
-    const unsigned long long v = (in && lane < 63) ? hitw[hit_word_index(p, 0, stride)] << (lane + 1) : 0ull;
+    unsigned long long v = 0;
+    if (p < m && lane < 63) {  // position P0 + lane + 1 is tail offset 0 of task p
+        const int32_t i = x.src[p];
+        const int32_t L = x.rowptr[i + 1] - p - 1;
+        if (L > 0 && hub_row[col[p]]) {
+            const int64_t w = hwoff[i + 1] - hit_words_upto(L);
+            if (w < hit_cap) v = hitw[w] << (lane + 1);
+        }
+    }
     uint32_t add = (uint32_t)__popcll(transpose64(v, lane));
     const int32_t r0 = x.src[P0];  // the row holding P0
     const int32_t r0s = x.rowptr[r0], r0e = x.rowptr[r0 + 1];
     if (r0s < P0) {
-        for (int32_t j0 = max(r0s, P0 - 64 * kHitWords); j0 < P0; j0 += 64) {
+        const int64_t rend = hwoff[r0 + 1];
+        for (int32_t j0 = r0s; j0 < P0; j0 += 64) {
             const int32_t j = j0 + lane;
             unsigned long long w = 0;
             if (j < P0 && hub_row[col[j]]) {
-                const int32_t L = r0e - j - 1;   // tail length of task j
+                const int32_t L = r0e - j - 1;   // tail length of task j (> P0 - j - 1)
                 const int32_t t0 = P0 - j - 1;   // tail offset of position P0 (>= 0)
                 const int32_t c = t0 >> 6, sft = t0 & 63;
-                const unsigned long long lo =
-                    (c < kHitWords && c * 64 < L) ? hitw[hit_word_index(j, c, stride)] : 0ull;
-                const unsigned long long hi =
-                    (c + 1 < kHitWords && (c + 1) * 64 < L) ? hitw[hit_word_index(j, c + 1, stride)] : 0ull;
+                const int64_t wc = rend - hit_words_upto(L) + c;  // word c exists: 64 c <= t0 < L
+                const unsigned long long lo = wc < hit_cap ? hitw[wc] : 0ull;
+                const unsigned long long hi = ((c + 1) * 64 < L && wc + 1 < hit_cap) ? hitw[wc + 1] : 0ull;
                 w = sft ? ((lo >> sft) | (hi << (64 - sft))) : lo;
             }
             add += (uint32_t)__popcll(transpose64(w, lane));
         }
     }
-    if (in && add) x.S[p] += (int32_t)add;
+    if (p < m && add) x.S[p] += (int32_t)add;
 }
 
-// Measurement aid (profiling only): the merge-model work of the pass, sum over
-// alive edges e = (i, kappa) of |tail of e in row i| + |row kappa|, and the sum
-// of the supports (three times the triangles), added to acc[0] and acc[1].
+// Measurement aid (profiling only): statistics of the pass just computed,
+// added to acc[0 .. kPassStats-1] (see PassStat).  hub_row: the rows kappa
+// the hub kernel staged in this pass, or null when it did not run.
 __global__ __launch_bounds__(kBlock) void k_pass_work(Buf x, const int32_t* __restrict__ count,
-                                                    const Ctl* __restrict__ ctl, unsigned long long* __restrict__ acc) {
-    __shared__ unsigned long long s_w[kBlock / 64], s_s[kBlock / 64];
+                                                    const uint8_t* __restrict__ hub_row,
+                                                    unsigned long long* __restrict__ acc) {
+    __shared__ unsigned long long s_v[kPassStats][kBlock / 64];
     const int32_t m = *count;
-    unsigned long long w = 0, sup = 0;
+    unsigned long long v[kPassStats] = {};
     for (int32_t e = (int32_t)(blockIdx.x * kBlock + threadIdx.x); e < m; e += (int32_t)(gridDim.x * kBlock)) {
-        const int32_t k = x.col[e];
-        w += (unsigned long long)(x.rowptr[x.src[e] + 1] - e - 1) + (unsigned long long)(x.rowptr[k + 1] - x.rowptr[k]);
-        sup += (unsigned long long)x.S[e];
+        const int32_t i = x.src[e], k = x.col[e];
+        const uint32_t tail = (uint32_t)(x.rowptr[i + 1] - e - 1);
+        v[kStatTail] += tail;
+        v[kStatRowK] += (uint32_t)(x.rowptr[k + 1] - x.rowptr[k]);
+        v[kStatSupport] += (uint32_t)x.S[e];
+        v[kStatEdges] += 1;
+        if (hub_row) {
+            if (hub_row[k]) {
+                v[kStatHubTasks] += 1;
+                v[kStatHubTail] += tail;
+                v[kStatHubWords] += (tail + 63) >> 6;
+            }
+            if (hub_row[i]) v[kStatHubStaged] += 1;
+        }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        w += __shfl_xor(w, o);
-        sup += __shfl_xor(sup, o);
-    }
-    if ((threadIdx.x & 63) == 0) {
-        s_w[threadIdx.x >> 6] = w;
-        s_s[threadIdx.x >> 6] = sup;
+    for (int j = 0; j < kPassStats; ++j) {
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[j] += __shfl_xor(v[j], o);
+        if ((threadIdx.x & 63) == 0) s_v[j][threadIdx.x >> 6] = v[j];
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 1; i < kBlock / 64; ++i) {
-            w += s_w[i];
-            sup += s_s[i];
-        }
-        atomicAdd(&acc[0], w);
-        atomicAdd(&acc[1], sup);
+    if (threadIdx.x < kPassStats) {
+        unsigned long long t = 0;
+        for (int i = 0; i < kBlock / 64; ++i) t += s_v[threadIdx.x][i];
+        if (t) atomicAdd(&acc[threadIdx.x], t);
     }
-    (void)ctl;
 }
 
 }  // namespace
 
-hipError_t launch_pass_work(const Buf& x, const int32_t* m_count, int32_t m_hint, const Ctl* ctl,
+hipError_t launch_pass_work(const Buf& x, const int32_t* m_count, int32_t m_hint, const uint8_t* hub_row,
                             unsigned long long* acc, hipStream_t s) {
     if (m_hint <= 0) return hipSuccess;
-    k_pass_work<<<min(grid_for(m_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, m_count, ctl, acc);
+    k_pass_work<<<min(grid_for(m_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, m_count, hub_row, acc);
     return hipGetLastError();
 }
 
@@ -496,7 +515,7 @@ hipError_t launch_support_hub(const Buf& x, const Csc& c, const Scratch& sc, int
                               unsigned long long* cycles, hipStream_t s) {
     if (n_items_hint <= 0) return hipSuccess;
     k_support_hub<<<min(n_items_hint, kHubMaxGrid), kHubThreads, 0, s>>>(x, c, sc.items, sc.ctail, ctl, sc.hitw,
-                                                                        sc.hit_stride, cycles);
+                                                                        sc.hwoff, sc.hit_cap, cycles);
     return hipGetLastError();
 }
 
@@ -505,7 +524,7 @@ hipError_t launch_hit_sum(const Buf& x, const Scratch& sc, const int32_t* m_coun
     if (m_hint <= 0) return hipSuccess;
     const int64_t windows = ((int64_t)m_hint + 63) / 64;
     const unsigned grid = (unsigned)((windows + kBlock / 64 - 1) / (kBlock / 64));  // one wave per window
-    k_hit_sum<<<grid, kBlock, 0, s>>>(x, sc.hitw, sc.hit_stride, sc.hub_row, m_count, ctl);
+    k_hit_sum<<<grid, kBlock, 0, s>>>(x, sc.hitw, sc.hwoff, sc.hit_cap, sc.hub_row, m_count, ctl);
     return hipGetLastError();
 }
 

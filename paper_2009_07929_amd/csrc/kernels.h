@@ -30,9 +30,24 @@ hipError_t launch_prune_canonical(const int32_t* support, uint8_t* alive, int32_
 // graphs finished in this pass are written to the outputs and dropped, and
 // the run ends when no edge is left.  m_hint bounds the alive edges, csc_hint
 // the in-edge list entries (the run's m: removed edges stay as tombstones).
+// Incremental support maintenance of a prune round (mode 0, one graph, with
+// in-edge lists): the survivors keep their supports, the removed edges are
+// listed (in Scratch::thread_tasks) and k_peel takes the destroyed triangles
+// off the survivors' supports.  ratio > 0: the peel is skipped, and
+// Ctl::need_support set, when more than ratio x the survivors were removed.
+struct PeelSpec {
+    bool on;
+    int32_t ratio;
+};
 hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* cy, int32_t n, int mode, int32_t thr,
                           const uint8_t* alive_can, const BatchCtx& b, Scratch& sc, Ctl* ctl, int p, int32_t m_hint,
-                          int32_t csc_hint, hipStream_t s);
+                          int32_t csc_hint, const PeelSpec& peel, hipStream_t s);
+// The peel itself (k_peel.hip), on buffer x's graph, survivors' supports in y.
+hipError_t launch_peel(const Buf& x, const Buf& y, const Csc& c, const int32_t* xscan, const int32_t* frontier,
+                       Ctl* ctl, int p, int32_t ratio, int32_t m_hint, hipStream_t s);
+// Zeroes the supports of buffer p's alive edges (a recomputation follows a
+// round whose compaction kept them).
+hipError_t launch_zero_support(const Buf& x, const Ctl* ctl, int p, int32_t m_hint, hipStream_t s);
 
 // ---- batched form (k_batch.hip)
 hipError_t launch_batch_setup(const BatchCtx& b, int32_t G, int32_t n_total, const int32_t* K, const int32_t* src,
@@ -42,6 +57,19 @@ hipError_t launch_batch_status(const Buf& x, const BatchCtx& b, int32_t G, const
                                const Ctl* ctl, hipStream_t s);
 
 // ---- scheduling structures (k_sched.hip)
+// Stable transpose of CSR columns (radix sort of (column, position) pairs):
+// columns ascending into keys_out, their positions into vals_out, ptr[0..n].
+// tk, tv: int32[m] ping-pong buffers distinct from the outputs.
+hipError_t launch_radix_transpose(const int32_t* keys, int32_t m, int32_t n, int32_t* keys_out, int32_t* vals_out,
+                                  int32_t* ptr, int32_t* const tk[2], int32_t* const tv[2], Scratch& sc,
+                                  hipStream_t s);
+// out[j] = the row of CSR position pos[j].
+hipError_t launch_rows_of(const int32_t* rowptr, int32_t nrows, const int32_t* pos, int32_t m, int32_t* out,
+                          hipStream_t s);
+// Butterfly task offsets: off[p] = sum over q < p of the tasks of pair vertex
+// q (0 without wedges, 1 if W(q) <= hash_max, else nwin), off[nP] = total.
+hipError_t launch_bf_task_offsets(const int64_t* W, int32_t nP, int64_t hash_max, int64_t nwin, int64_t* off,
+                                  Scratch& sc, hipStream_t s);
 hipError_t launch_build_csc(const Buf& b, const Csc& c, int32_t n, int32_t m, Scratch& sc, hipStream_t s);
 // Work lists of one support pass over buffer p: hub items (all rows with
 // work under FORCE_HUB; the hub rows of the heuristic or of `learned_hub`
@@ -62,9 +90,9 @@ hipError_t launch_support_wave(const Buf& x, const int32_t* tasks, const int32_t
 // cycles: per-row shader-clock totals of the hub items (cost-model samples), or null
 hipError_t launch_support_hub(const Buf& x, const Csc& c, const Scratch& sc, int32_t n_items_hint, Ctl* ctl,
                               unsigned long long* cycles, hipStream_t s);
-// Profiling: merge-model work and support sum of the pass just computed, added
-// to acc[0] and acc[1].
-hipError_t launch_pass_work(const Buf& x, const int32_t* m_count, int32_t m_hint, const Ctl* ctl,
+// Profiling: statistics of the pass just computed (PassStat), added to
+// acc[0 .. kPassStats-1]; hub_row: rows the hub kernel staged, or null.
+hipError_t launch_pass_work(const Buf& x, const int32_t* m_count, int32_t m_hint, const uint8_t* hub_row,
                             unsigned long long* acc, hipStream_t s);
 // Row-local sum of the hub kernel's hit words into S (one wave per 64 edges;
 // m_count: alive edges on the device, m_hint: an upper bound for the grid).

@@ -32,7 +32,7 @@ class ktruss_tuning(ctypes.Structure):
     _fields_ = [("wave_min_work", ctypes.c_int32), ("hub_min_work", ctypes.c_int32),
                 ("hub_chunk_work", ctypes.c_int32), ("rounds_per_sync", ctypes.c_int32),
                 ("learned_hub_min", ctypes.c_float), ("hub_chunk_tasks", ctypes.c_int32),
-                ("plain_max_work", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("plain_max_work", ctypes.c_int32), ("incremental", ctypes.c_int32), ("peel_ratio", ctypes.c_int32)]
 
 
 MLP_IN, MLP_HIDDEN, MLP_PARAMS = 5, 64, 4609
@@ -73,7 +73,10 @@ def load():
         "ktruss_set_schedule": ([G, i32, p, ctypes.POINTER(ktruss_tuning)], i32),
         "ktruss_profile_enable": ([i32], i32),
         "ktruss_profile_read": ([i32, p, p, p, p], i32),
+        "ktruss_profile_stats": ([p, i32], i32),
         "ktruss_batch_workspace_bytes": ([i32, i64, i64, i32], i64),
+        "ktruss_butterfly_workspace_bytes": ([i32, i32, i64], i64),
+        "ktruss_butterflies": ([ctypes.POINTER(ktruss_bipartite), p, p, p], i32),
         "ktruss_run_batched": ([ctypes.POINTER(ktruss_batch), p, p, p, p, p], i32),
     }
     for name, (args, res) in sig.items():
@@ -212,6 +215,16 @@ def ktruss_profile_read(kind: int = PROFILE_PASS):
     return launches.value, ms.value, edges.value, nbytes.value
 
 
+PASS_STATS = ("edges", "tail", "rowk", "support", "hub_tasks", "hub_tail", "hub_words", "hub_staged")
+
+
+def ktruss_profile_stats():
+    """Pass statistics summed over the profiled passes, as a dict keyed by PASS_STATS."""
+    out = (ctypes.c_int64 * len(PASS_STATS))()
+    _check(load().ktruss_profile_stats(out, len(PASS_STATS)))
+    return dict(zip(PASS_STATS, (int(v) for v in out)))
+
+
 def ktruss_run(g: Graph, K: int, mask=None, support=None, stream=None):
     """Full fixpoint.  Returns (mask uint8[m], support int32[m], rounds)."""
     import torch
@@ -242,6 +255,46 @@ class ktruss_batch(ctypes.Structure):
                 ("m_total", ctypes.c_int64), ("vert_off", ctypes.c_void_p), ("rowptr", ctypes.c_void_p),
                 ("col", ctypes.c_void_p), ("work", ctypes.c_void_p), ("work_bytes", ctypes.c_int64),
                 ("tuning", ktruss_tuning)]
+
+
+class ktruss_bipartite(ctypes.Structure):
+    _fields_ = [("nu", ctypes.c_int32), ("nv", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("work", ctypes.c_void_p),
+                ("work_bytes", ctypes.c_int64)]
+
+
+def ktruss_butterfly_workspace_bytes(nu: int, nv: int, m: int) -> int:
+    r = load().ktruss_butterfly_workspace_bytes(nu, nv, m)
+    if r < 0:
+        _check(int(r))
+    return int(r)
+
+
+def ktruss_butterflies(nu: int, nv: int, rowptr, col, device="cuda", count=None, stream=None, work=None):
+    """Butterflies of the bipartite graph with CSR rows over U (columns in [0, nv)):
+    (count int64[m] device tensor per edge, total).  work: a device uint8 tensor of
+    at least ktruss_butterfly_workspace_bytes + 256 bytes, or None (allocated here)."""
+    import torch
+    rp = torch.as_tensor(np.ascontiguousarray(rowptr, np.int32) if isinstance(rowptr, np.ndarray) else rowptr)
+    cl = torch.as_tensor(np.ascontiguousarray(col, np.int32) if isinstance(col, np.ndarray) else col)
+    m = int(cl.numel())
+    rp = rp.to(device=device, dtype=torch.int32).contiguous()
+    cl = (cl if m else torch.zeros(1, dtype=torch.int32)).to(device=device, dtype=torch.int32).contiguous()
+    nbytes = ktruss_butterfly_workspace_bytes(nu, nv, m)
+    if work is None:
+        work = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    elif work.numel() < nbytes + 256:
+        raise ValueError("butterfly workspace too small")
+    base = (work.data_ptr() + 255) & ~255
+    if count is None:
+        count = torch.empty(max(m, 1), dtype=torch.int64, device=device)
+    g = ktruss_bipartite()
+    g.nu, g.nv, g.m = nu, nv, m
+    g.rowptr, g.col = rp.data_ptr(), cl.data_ptr()
+    g.work, g.work_bytes = base, int(nbytes)
+    total = ctypes.c_int64()
+    _check(load().ktruss_butterflies(ctypes.byref(g), _ptr(count), ctypes.byref(total), _stream(stream)))
+    return count[:m], total.value
 
 
 def ktruss_batch_workspace_bytes(G: int, n_total: int, m_total: int, flags: int = 0) -> int:
