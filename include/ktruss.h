@@ -65,21 +65,24 @@ typedef struct ktruss_tuning {
     int32_t wave_min_work;   /* heuristic/learned: non-hub edge tasks whose merge length (row tail + row kappa)
                                 is at least this use wavefront-per-edge, the others thread-per-edge */
     int32_t hub_min_work;    /* heuristic: rows kappa selected by at least this many tasks are hub rows */
-    int32_t hub_chunk_work;  /* learned: predicted shader cycles per hub item when a hub row is split */
+    int32_t hub_chunk_work;  /* unused (kept for the layout) */
     int32_t rounds_per_sync; /* <= 1: host checks the fixpoint after every round (exact grids);
                                 >= 2: rounds are captured in a hipGraph and replayed this many at a time */
-    float learned_hub_min;   /* learned: rows whose predicted log2 cycles reach this are hub rows (0: 12) */
-    int32_t hub_chunk_tasks; /* heuristic/force-hub: tasks per hub item (clamped to 16..256) */
+    float learned_hub_min;   /* learned: rows whose predicted log2 (hub cost / wavefront cost) is at most this
+                                are hub rows (0: the default 0) */
+    int32_t hub_chunk_tasks; /* heuristic/force-hub/learned: tasks per hub item (clamped to 16..256) */
     int32_t plain_max_work;  /* heuristic/learned: if the input's mean merge length per edge (row tail + row
                                 kappa; the row-kappa lengths sampled on edges 0, 16, 32, ... and weighted
                                 by 16) is at most this, ktruss_run/ktruss_support use thread-per-edge for
                                 every task and build no in-edge lists; 0: default 32, negative: never */
-    int32_t incremental;     /* ktruss_run / ktruss_decompose: 0 recompute every pass's supports (Algorithm 1);
+    int32_t incremental;     /* ktruss_run / ktruss_decompose / ktruss_run_batched: 0 recompute every pass's supports (Algorithm 1);
                                 1 after the first pass, keep the survivors' supports and take off each triangle a
                                 prune destroys (incremental maintenance); 2 as 1, except that a prune removing
                                 more than peel_ratio x the edges it keeps is followed by a recomputation.  Masks,
                                 supports and pass counts are the same in every mode.  Rounds replayed from a
-                                hipGraph (rounds_per_sync >= 2) use mode 1 for 2.  The batched form recomputes. */
+                                hipGraph (rounds_per_sync >= 2) use mode 1 for 2.  Also for ktruss_run_batched
+                                (the edges of a graph that finishes leave the working set without destroying
+                                triangles). */
     int32_t peel_ratio;      /* incremental = 2: the ratio above (0: 1) */
 } ktruss_tuning;
 
@@ -319,28 +322,35 @@ int32_t ktruss_profile_stats(int64_t* out, int32_t len);
 
 /* ------------------------------------------------------------- cost model */
 /*
- * The LEARNED schedule predicts, for every row kappa of A22 that the tasks of
- * a pass select (Algorithm 3), the shader cycles its support work costs on
- * the workgroup-per-hub-row kernel, from five features: its out-degree, log2
- * of it, log2 of the sum of the out-degrees of the rows whose tasks select it,
- * the pass index, and the fraction of the input's edges still alive.  Rows
- * predicted expensive become hub rows, split into items of about
- * tuning.hub_chunk_work predicted cycles; the other tasks go to the
- * wavefront- or thread-per-edge kernels.  Scheduling only: results never
- * depend on the model.  The model is trained on samples from
- * ktruss_collect_row_costs with the calls below.
+ * The LEARNED schedule decides, for every row kappa of A22 that the tasks of
+ * a pass select (Algorithm 3), which kernel variant runs those tasks: the
+ * workgroup-per-hub-row kernel or the per-edge kernels.  Section III-B notes
+ * that grouping work exactly can cost as much as the work; the cost model
+ * predicts instead, from five features of the row (its out-degree, log2 of
+ * it, log2 of the sum of the out-degrees of the rows whose tasks select it,
+ * the pass index, the fraction of the input's edges still alive), the log2
+ * ratio of the row's cost on the hub kernel to its cost on the
+ * wavefront-per-edge kernel (both in wave-cycles).  Rows predicted at most
+ * tuning.learned_hub_min (default 0: the hub kernel is cheaper) become hub
+ * rows, in items of tuning.hub_chunk_tasks tasks; the tasks of the others go
+ * to the wavefront- or thread-per-edge kernel by merge length.  Scheduling
+ * only: results never depend on the model.  The model is trained on samples
+ * from ktruss_collect_row_costs with the calls below.
  */
 
 /*
- * ktruss_collect_row_costs — runs the fixpoint of g for K under the hub
- * schedule with the hub kernel timed per row, and appends one sample per
- * active row and pass: features (device float[capacity*5]) and the measured
- * cost as log2(1 + shader cycles) (device float[capacity]).  count (host)
- * receives the number of samples written (at most capacity).  Outputs of the
- * truss itself are not produced.  Synchronises `stream`.
+ * ktruss_collect_row_costs — runs the fixpoint of g for K with every task on
+ * one kernel variant (variant 0: workgroup-per-hub-row, 1: wavefront-per-edge),
+ * timed per row with the shader clock, and appends one sample per active row
+ * and pass: features (device float[capacity*5]) and the measured cost as
+ * log2(1 + wave-cycles) (device float[capacity]; a hub item's cycles count
+ * once per wave of its workgroup).  Both variants visit the same rows in the
+ * same order, so their samples pair up.  count (host) receives the number of
+ * samples written (at most capacity).  The truss itself is not output.
+ * Synchronises `stream`.
  */
-int32_t ktruss_collect_row_costs(const ktruss_graph* g, int32_t K, float* features, float* costs, int32_t capacity,
-                                 int32_t* count, void* stream);
+int32_t ktruss_collect_row_costs(const ktruss_graph* g, int32_t K, int32_t variant, float* features, float* costs,
+                                 int32_t capacity, int32_t* count, void* stream);
 
 /* Scratch bytes needed by ktruss_mlp_loss_grad for `rows` samples. */
 int64_t ktruss_mlp_workspace_bytes(int32_t rows);

@@ -27,7 +27,7 @@ SCHEDULE_IDS = {"plain": kt.SCHED_PLAIN, "heuristic": kt.SCHED_HEURISTIC, "learn
                 "hub": kt.SCHED_FORCE_HUB}
 
 DEFAULT = {"schedule": "hub", "hub_chunk_tasks": 256, "hub_min_work": 8, "wave_min_work": 192,
-           "hub_chunk_work": 400000, "learned_hub_min": 12.0, "rounds_per_sync": 0, "plain_max_work": 0}
+           "hub_chunk_work": 0, "learned_hub_min": 0.0, "rounds_per_sync": 0, "plain_max_work": 0}
 
 # values tried per knob (coordinate search, in this order)
 SPACE = [
@@ -36,13 +36,12 @@ SPACE = [
     ("rounds_per_sync", [0, 4, 16]),
     ("hub_min_work", [2, 8, 32]),
     ("wave_min_work", [64, 192, 768]),
-    ("learned_hub_min", [8.0, 12.0, 16.0]),
-    ("hub_chunk_work", [100000, 400000, 1600000]),
+    ("learned_hub_min", [-0.5, 0.0, 0.5]),
     ("plain_max_work", [-1, 0, 128]),
 ]
 # knobs that only matter under some schedules
 RELEVANT = {"hub_min_work": {"heuristic"}, "wave_min_work": {"heuristic", "learned"},
-            "learned_hub_min": {"learned"}, "hub_chunk_work": {"learned"}, "hub_chunk_tasks": {"hub", "heuristic"},
+            "learned_hub_min": {"learned"}, "hub_chunk_tasks": {"hub", "heuristic", "learned"},
             "plain_max_work": {"heuristic", "learned"}, "rounds_per_sync": {"hub", "heuristic", "learned", "plain"}}
 
 
@@ -65,7 +64,6 @@ def to_tuning(cfg) -> kt.ktruss_tuning:
     t.hub_chunk_tasks = int(cfg["hub_chunk_tasks"])
     t.hub_min_work = int(cfg["hub_min_work"])
     t.wave_min_work = int(cfg["wave_min_work"])
-    t.hub_chunk_work = int(cfg["hub_chunk_work"])
     t.learned_hub_min = float(cfg["learned_hub_min"])
     t.rounds_per_sync = int(cfg["rounds_per_sync"])
     t.plain_max_work = int(cfg.get("plain_max_work", 0))

@@ -370,7 +370,7 @@ int32_t support_pass(int sched, int32_t n, const Work& w, int p, const PassDims&
             rc = timed_launch(4, dm.m, s, [&] { return launch_hit_sum(x, w.sc, &w.ctl->m_buf[p], dm.m, w.ctl, s); });
         if (rc == KTRUSS_OK && sched != KTRUSS_SCHED_FORCE_HUB) {
             rc = timed_launch(2, dm.n_wave, s, [&] {
-                return launch_support_wave(x, w.sc.wave_tasks, &w.ctl->n_wave, dm.n_wave, w.ctl, s);
+                return launch_support_wave(x, w.sc.wave_tasks, &w.ctl->n_wave, dm.n_wave, w.ctl, s, cycles);
             });
             if (rc == KTRUSS_OK)
                 rc = timed_launch(1, dm.n_thread, s, [&] {
@@ -895,7 +895,6 @@ int32_t ktruss_run_batched(const ktruss_batch* b, const int32_t* K, uint8_t* mas
         return KTRUSS_OK;
     }
     RunSpec r = make_spec(n, m, b->rowptr, b->col, b->schedule, b->tuning, nullptr);
-    r.incremental = 0;  // graphs finishing inside a pass are written out by the compaction
     r.G = G;
     r.K = K;
     r.rounds_dev = rounds;
@@ -914,12 +913,13 @@ int32_t ktruss_run_batched(const ktruss_batch* b, const int32_t* K, uint8_t* mas
 
 // ---------------------------------------------------------------- cost model
 
-int32_t ktruss_collect_row_costs(const ktruss_graph* g, int32_t K, float* features, float* costs, int32_t capacity,
-                                 int32_t* count, void* stream) {
+int32_t ktruss_collect_row_costs(const ktruss_graph* g, int32_t K, int32_t variant, float* features, float* costs,
+                                 int32_t capacity, int32_t* count, void* stream) {
     clear_error();
     int32_t rc = check_graph(g, true);
     if (rc != KTRUSS_OK) return rc;
     if (K < 2) return fail(KTRUSS_E_INVALID, "K must be >= 2 (got %d)", K);
+    if (variant != 0 && variant != 1) return fail(KTRUSS_E_INVALID, "variant must be 0 (hub) or 1 (wavefront)");
     if (capacity < 0 || (capacity > 0 && (!features || !costs)) || !count)
         return fail(KTRUSS_E_INVALID, "sample buffers are null or capacity < 0");
     hipStream_t s = (hipStream_t)stream;
@@ -932,7 +932,7 @@ int32_t ktruss_collect_row_costs(const ktruss_graph* g, int32_t K, float* featur
     ktruss_tuning t = g->tuning;
     t.rounds_per_sync = 0;
     t.incremental = 0;  // every pass is a timed support pass
-    RunSpec r = make_spec(n, m, g->rowptr, g->col, KTRUSS_SCHED_FORCE_HUB, t, nullptr);
+    RunSpec r = make_spec(n, m, g->rowptr, g->col, variant == 0 ? KTRUSS_SCHED_FORCE_HUB : kSchedSampleWave, t, nullptr);
     r.thr = K - 2;
     r.collect = true;
     r.capacity = capacity;

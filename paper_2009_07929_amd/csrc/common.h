@@ -30,11 +30,16 @@ constexpr int kMlpGradMaxBlocks = 512;   // workgroups of the cost-model gradien
 constexpr int kRsTile = 4096;            // (column, edge) pairs per workgroup of the radix-sort transpose
 constexpr int kHitWordsPerEdge = 8;      // hit-word capacity of the workspace per edge (see hit_words_upto)
 
-// learned schedule defaults (predicted log2 shader cycles of a row's hub work)
-constexpr float kDefaultLearnedHubMin = 12.0f;
+// learned schedule: the cost model predicts, for a row kappa, log2 of its
+// wave-cycles on the hub kernel minus log2 of its wave-cycles on the
+// wavefront-per-edge kernel; the row goes to the hub kernel when the
+// prediction is at most the threshold (default 0: the hub kernel is cheaper)
+constexpr float kDefaultLearnedHubMax = 0.0f;
 constexpr int32_t kDefaultPlainMaxWork = 32;
-constexpr float kDefaultLearnedChunk = 400000.0f;
 constexpr int kMinLearnedChunk = 16;     // fewest tasks per hub item
+// internal schedule of cost sampling: every task on the wavefront kernel,
+// through the binned path (in-edge lists, row features, per-row timing)
+constexpr int kSchedSampleWave = 100;
 
 // static degree heuristic defaults
 constexpr int kDefaultHubMinIn = 8;    // in-edges for a row kappa to be a hub row

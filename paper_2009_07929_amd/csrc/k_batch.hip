@@ -15,26 +15,36 @@ namespace kt {
 
 namespace {
 
-// Per graph: its vertex range is [vert_off[g], vert_off[g+1]).  Writes the
-// vertex -> graph map and the per-vertex threshold, checks K_g >= 2 and the
-// offsets (err bit 32).
-__global__ __launch_bounds__(kBlock) void k_batch_vertices(const int32_t* __restrict__ vert_off,
-                                                         const int32_t* __restrict__ K, int32_t G, int32_t n_total,
-                                                         int32_t* __restrict__ gidv, int32_t* __restrict__ thrv,
-                                                         Ctl* ctl) {
+// Per graph: its vertex range is [vert_off[g], vert_off[g+1]); checks K_g >= 2
+// and the offsets (err bit 32).
+__global__ __launch_bounds__(kBlock) void k_batch_graphs(const int32_t* __restrict__ vert_off,
+                                                       const int32_t* __restrict__ K, int32_t G, int32_t n_total,
+                                                       Ctl* ctl) {
     const int32_t g = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
     if (g >= G) return;
     const int32_t v0 = vert_off[g], v1 = vert_off[g + 1];
-    const int32_t k = K[g];
-    const bool bad = v0 < 0 || v1 < v0 || v1 > n_total || (g == 0 && v0 != 0) || (g == G - 1 && v1 != n_total) || k < 2;
-    if (bad) {
-        atomicOr(&ctl->err, 32);
-        return;
+    const bool bad = v0 < 0 || v1 < v0 || v1 > n_total || (g == 0 && v0 != 0) || (g == G - 1 && v1 != n_total) ||
+                     K[g] < 2;
+    if (bad) atomicOr(&ctl->err, 32);
+}
+
+// One thread per vertex: its graph (last g with vert_off[g] <= v, by binary
+// search over the checked offsets) and that graph's threshold.
+__global__ __launch_bounds__(kBlock) void k_batch_vertices(const int32_t* __restrict__ vert_off,
+                                                         const int32_t* __restrict__ K, int32_t G, int32_t n_total,
+                                                         int32_t* __restrict__ gidv, int32_t* __restrict__ thrv,
+                                                         const Ctl* __restrict__ ctl) {
+    if (ctl->err) return;
+    const int32_t v = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (v >= n_total) return;
+    int32_t lo = 0, hi = G;  // vert_off[lo] <= v < vert_off[hi]
+    while (hi - lo > 1) {
+        const int32_t mid = lo + ((hi - lo) >> 1);
+        if (vert_off[mid] <= v) lo = mid;
+        else hi = mid;
     }
-    for (int32_t v = v0; v < v1; ++v) {
-        gidv[v] = g;
-        thrv[v] = k - 2;
-    }
+    gidv[v] = lo;
+    thrv[v] = K[lo] - 2;
 }
 
 // Every edge must stay inside its graph (err bit 64).
@@ -88,7 +98,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_status(Buf x, const int32_t* _
 
 hipError_t launch_batch_setup(const BatchCtx& b, int32_t G, int32_t n_total, const int32_t* K, const int32_t* src,
                               const int32_t* col, int32_t m, Ctl* ctl, hipStream_t s) {
-    if (G > 0) k_batch_vertices<<<grid_for(G), kBlock, 0, s>>>(b.vert_off, K, G, n_total, b.gidv, b.thrv, ctl);
+    if (G > 0) k_batch_graphs<<<grid_for(G), kBlock, 0, s>>>(b.vert_off, K, G, n_total, ctl);
+    if (G > 0 && n_total > 0)
+        k_batch_vertices<<<grid_for(n_total), kBlock, 0, s>>>(b.vert_off, K, G, n_total, b.gidv, b.thrv, ctl);
     if (m > 0) k_batch_edges<<<grid_for(m), kBlock, 0, s>>>(src, col, m, b.vert_off, b.gidv, ctl);
     return hipGetLastError();
 }

@@ -39,8 +39,11 @@ struct CsrRound {
     __device__ int32_t load(int32_t e) const { return e; }
     __device__ bool keep(int32_t e) const { return round_keep(x, b, thr, e); }
     __device__ void drop(int32_t e, int32_t i, int32_t q) const {
-        if (frontier) frontier[i - q] = e;
-        if (b.thrv && b.done_now[b.gidv[x.src[e]]]) {
+        // an edge of a graph finished in this pass leaves the working set
+        // without leaving its truss: it destroys no triangle (-1 in the list)
+        const bool finished = b.thrv && b.done_now[b.gidv[x.src[e]]];
+        if (frontier) frontier[i - q] = finished ? -1 : e;
+        if (finished) {
             const int32_t c = x.eid[e];
             b.mask[c] = 1;
             b.support[c] = x.S[e];
@@ -355,7 +358,7 @@ hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* 
                           int32_t csc_hint, const PeelSpec& peel, hipStream_t s) {
     const int round = mode == 0;
     const bool batch = b.thrv != nullptr;
-    const bool inc = peel.on && mode == 0 && !batch && cx;
+    const bool inc = peel.on && mode == 0 && cx;
     if (mode == 0) {
         run_filter(CsrRound{x, y, thr, b, inc ? sc.thread_tasks : nullptr}, ctl, p, batch ? 3 : 1, 1, sc.blockcnt,
                    sc.blockoff, sc.xscan, m_hint, s);

@@ -79,6 +79,7 @@ __global__ __launch_bounds__(kBlock) void k_peel(Buf x, Buf y, Csc c, const int3
     const int32_t nw = (int32_t)(gridDim.x * (kBlock / 64));
     for (int32_t wid = (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 6); wid < nf; wid += nw) {
         const int32_t f = frontier[wid];
+        if (f < 0) continue;  // an edge of a finished graph (batched form): its triangles stay
         const int32_t u = x.src[f], v = col[f];
         // charge the triangle (f, e1, e2) here unless a removed edge with a
         // smaller position is in it; decrement its surviving edges

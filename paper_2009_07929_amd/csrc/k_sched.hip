@@ -415,26 +415,17 @@ __global__ __launch_bounds__(kBlock) void k_row_features(const int32_t* __restri
     for (int i = 0; i < KTRUSS_MLP_IN; ++i) feats[(int64_t)a * KTRUSS_MLP_IN + i] = f[i];
 }
 
-// Bins from the predicted log2 cycles of each active row: hub row if at least
-// hub_min; a hub row is split into items of about `target` predicted cycles.
+// Bins from the cost model's prediction for each active row: log2 of the
+// row's wave-cycles on the hub kernel minus log2 of them on the wavefront
+// kernel.  A row predicted at most `thr` is a hub row (items of the common
+// chunk size); the others' tasks go to the wavefront / thread lists.
 __global__ __launch_bounds__(kBlock) void k_learned_bins(const int32_t* __restrict__ list, const float* __restrict__ pred,
-                                                       const int32_t* __restrict__ cptr, float hub_min, float target,
-                                                       uint8_t* __restrict__ is_hub, int32_t* __restrict__ chunk_sz,
+                                                       float thr, uint8_t* __restrict__ is_hub,
                                                        const Ctl* __restrict__ ctl) {
     if (ctl->done) return;
     const int32_t a = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
     if (a >= ctl->n_active) return;
-    const int32_t k = list[a];
-    const float lp = pred[a];
-    const bool hub = lp >= hub_min;
-    is_hub[k] = hub ? 1 : 0;
-    if (hub) {
-        const int32_t indeg = cptr[k + 1] - cptr[k];
-        const float pieces = fminf(exp2f(fminf(lp, 40.f)) / target, (float)indeg);
-        int32_t cs = (int32_t)ceilf((float)indeg / fmaxf(pieces, 1.f));
-        cs = max(kMinLearnedChunk, min(cs, kHubChunk));
-        chunk_sz[k] = cs;
-    }
+    is_hub[list[a]] = pred[a] <= thr ? 1 : 0;  // a NaN prediction leaves the row off the hub kernel
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_u8(uint8_t* __restrict__ a, int32_t n, uint8_t v) {
@@ -696,6 +687,10 @@ hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched,
         k_task_tails<<<min(grid_for(m0), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, c, ctl, sc.ctail);
     // first hit word of every row's tasks (a 64-bit scan of the rows' word counts)
     device_scan64(RowWords{x.rowptr}, n, ctl, sc, sc.hwoff, s);
+    if (sched == kSchedSampleWave) {  // cost sampling: no hub rows, every task on the wavefront kernel
+        k_fill_u8<<<grid_for(n), kBlock, 0, s>>>(sc.is_hub, n, 0);
+        is_hub = sc.is_hub;
+    }
     if (sched == KTRUSS_SCHED_HEURISTIC || (sched == KTRUSS_SCHED_LEARNED && !mlp)) {
         const int32_t hub_min_in = t.hub_min_work > 0 ? t.hub_min_work : kDefaultHubMinIn;
         k_heuristic_bins<<<grid_for(n), kBlock, 0, s>>>(x.rowptr, sc.alive_in, n, hub_min_in, sc.is_hub, ctl);
@@ -711,13 +706,10 @@ hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched,
     if (learned) {
         hipError_t e = launch_mlp_forward_dev(mlp, sc.feats, &ctl->n_active, n, sc.pred, s);
         if (e != hipSuccess) return e;
-        const float hub_min = t.learned_hub_min > 0.f ? t.learned_hub_min : kDefaultLearnedHubMin;
-        const float target = t.hub_chunk_work > 0 ? (float)t.hub_chunk_work : kDefaultLearnedChunk;
+        const float thr = t.learned_hub_min != 0.f ? t.learned_hub_min : kDefaultLearnedHubMax;
         k_fill_u8<<<grid_for(n), kBlock, 0, s>>>(sc.is_hub, n, 0);
-        k_learned_bins<<<grid_for(n), kBlock, 0, s>>>(sc.act_list, sc.pred, c.ptr, hub_min, target, sc.is_hub,
-                                                       sc.chunk_sz, ctl);
+        k_learned_bins<<<grid_for(n), kBlock, 0, s>>>(sc.act_list, sc.pred, thr, sc.is_hub, ctl);
         is_hub = sc.is_hub;
-        chunk = sc.chunk_sz;
     }
     // hub items (every row with work under FORCE_HUB)
     int32_t chunk_all = t.hub_chunk_tasks > 0 ? t.hub_chunk_tasks : kHubChunk;
@@ -726,7 +718,7 @@ hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched,
     device_scan(hc, n, ctl, sc, sc.itemoff, &ctl->n_items, s);
     k_hub_items<<<grid_for(n), kBlock, 0, s>>>(hc, x.col, n, sc.itemoff, sc.items, sc.hub_row, ctl);
     if (is_hub) {
-        const int32_t wave_min = t.wave_min_work > 0 ? t.wave_min_work : kDefaultWaveMin;
+        const int32_t wave_min = sched == kSchedSampleWave ? 0 : (t.wave_min_work > 0 ? t.wave_min_work : kDefaultWaveMin);
         TaskClass tc{x, c, is_hub, wave_min};
         const int32_t G = scan_grid(m0);  // the in-edge lists keep the run's m entries
         k_task_count<<<G, kBlock, 0, s>>>(tc, ctl, p, sc.blockcnt2);

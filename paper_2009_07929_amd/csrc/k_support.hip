@@ -14,7 +14,7 @@ namespace kt {
 namespace {
 
 __device__ __forceinline__ void thread_task(const Buf& x, int32_t e);
-__device__ __forceinline__ void wave_task(const Buf& x, int32_t e);
+__device__ __forceinline__ void wave_task(const Buf& x, int32_t e, unsigned long long* cycles);
 
 // ------------------------------------------------------ thread-per-edge
 // One thread per task: a merge of the two ascending lists (the mapping of the
@@ -64,23 +64,30 @@ __device__ __forceinline__ void thread_task(const Buf& x, int32_t e) {
 // binary-search each element in the other (both ascending, in global memory;
 // the first search steps of all lanes hit the same lines).  Hits bump the two
 // other edges' supports; the wave total goes to S[e] once.
+// cycles: when not null (cost sampling), every task's shader cycles are
+// added to cycles[kappa] (one wave per task: wave-cycles).
 __global__ __launch_bounds__(kBlock) void k_support_wave(Buf x, const int32_t* __restrict__ tasks,
-                                                       const int32_t* __restrict__ count, const Ctl* __restrict__ ctl) {
+                                                       const int32_t* __restrict__ count, const Ctl* __restrict__ ctl,
+                                                       unsigned long long* __restrict__ cycles) {
     if (ctl->done) return;
     const int32_t nt = *count;
     const int32_t nw = (int32_t)(gridDim.x * (kBlock / 64));
     for (int32_t wid = (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 6); wid < nt; wid += nw)
-        wave_task(x, tasks ? tasks[wid] : wid);
+        wave_task(x, tasks ? tasks[wid] : wid, cycles);
 }
 
-__device__ __forceinline__ void wave_task(const Buf& x, int32_t e) {
+__device__ __forceinline__ void wave_task(const Buf& x, int32_t e, unsigned long long* cycles) {
     const int lane = __lane_id();
+    const unsigned long long t0 = cycles ? (unsigned long long)clock64() : 0ull;
     const int32_t* __restrict__ col = x.col;
     const int32_t i = x.src[e];
     const int32_t k = col[e];
     const int32_t a0 = e + 1, a1 = x.rowptr[i + 1];     // tail of row i
     const int32_t b0 = x.rowptr[k], b1 = x.rowptr[k + 1];  // row kappa
-    if (a0 >= a1 || b0 >= b1) return;
+    if (a0 >= a1 || b0 >= b1) {
+        if (cycles && lane == 0) atomicAdd(&cycles[k], (unsigned long long)clock64() - t0);
+        return;
+    }
     const int32_t la = a1 - a0, lb = b1 - b0;
     // walk list W (positions w0..w1), search list F (f0..f1)
     const bool walk_tail = la <= lb;
@@ -105,6 +112,7 @@ __device__ __forceinline__ void wave_task(const Buf& x, int32_t e) {
     }
     cnt = wave_sum(cnt);
     if (lane == 0 && cnt) atomicAdd(&x.S[e], cnt);
+    if (cycles && lane == 0) atomicAdd(&cycles[k], (unsigned long long)clock64() - t0);
 }
 
 // ------------------------------------------------- workgroup-per-hub-row
@@ -365,7 +373,8 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
                                    cur_guard, s_bm, s_acc);
             if (cycles) {  // per-row cost samples for the cost model (shader clock)
                 __syncthreads();
-                if (t == 0) atomicAdd(&cycles[k], (unsigned long long)clock64() - t_start);
+                // wave-cycles: the item held the workgroup's kHubThreads / 64 waves
+                if (t == 0) atomicAdd(&cycles[k], ((unsigned long long)clock64() - t_start) * (kHubThreads / 64));
             }
         }
         __syncthreads();  // every thread has read s_it
@@ -505,9 +514,10 @@ hipError_t launch_support_thread(const Buf& x, const int32_t* tasks, const int32
 }
 
 hipError_t launch_support_wave(const Buf& x, const int32_t* tasks, const int32_t* count_dev, int32_t n_hint,
-                               const Ctl* ctl, hipStream_t s) {
+                               const Ctl* ctl, hipStream_t s, unsigned long long* cycles) {
     if (n_hint <= 0) return hipSuccess;
-    k_support_wave<<<min(grid_for((int64_t)n_hint * 64), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, tasks, count_dev, ctl);
+    k_support_wave<<<min(grid_for((int64_t)n_hint * 64), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, tasks, count_dev, ctl,
+                                                                                                  cycles);
     return hipGetLastError();
 }
 

@@ -85,9 +85,10 @@ hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched,
 hipError_t launch_support_thread(const Buf& x, const int32_t* tasks, const int32_t* count_dev, int32_t n_hint,
                                  const Ctl* ctl, hipStream_t s);
 hipError_t launch_support_row(const Buf& x, int32_t n, const Ctl* ctl, hipStream_t s);
+// cycles: per-row wave-cycles of the tasks (cost sampling), or null
 hipError_t launch_support_wave(const Buf& x, const int32_t* tasks, const int32_t* count_dev, int32_t n_hint,
-                               const Ctl* ctl, hipStream_t s);
-// cycles: per-row shader-clock totals of the hub items (cost-model samples), or null
+                               const Ctl* ctl, hipStream_t s, unsigned long long* cycles = nullptr);
+// cycles: per-row wave-cycles of the hub items (cost-model samples: shader clock x 4 waves), or null
 hipError_t launch_support_hub(const Buf& x, const Csc& c, const Scratch& sc, int32_t n_items_hint, Ctl* ctl,
                               unsigned long long* cycles, hipStream_t s);
 // Profiling: statistics of the pass just computed (PassStat), added to

@@ -384,7 +384,7 @@ def _cost_model_sigs(lib):
     i32, i64, p, f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p, ctypes.c_float
     G = ctypes.POINTER(ktruss_graph)
     for name, args, res in (
-            ("ktruss_collect_row_costs", [G, i32, p, p, i32, ctypes.POINTER(ctypes.c_int32), p], i32),
+            ("ktruss_collect_row_costs", [G, i32, i32, p, p, i32, ctypes.POINTER(ctypes.c_int32), p], i32),
             ("ktruss_mlp_workspace_bytes", [i32], i64),
             ("ktruss_mlp_forward", [p, p, i32, p, p], i32),
             ("ktruss_mlp_loss_grad", [p, p, p, i32, p, p, p, i64, p], i32),
@@ -394,16 +394,17 @@ def _cost_model_sigs(lib):
         f.restype = res
 
 
-def ktruss_collect_row_costs(g: Graph, K: int, capacity: int, stream=None):
-    """Per-row cost samples of a timed hub-schedule run: (features float[count,5], log2 cycles float[count])."""
+def ktruss_collect_row_costs(g: Graph, K: int, capacity: int, stream=None, variant: int = 0):
+    """Per-row cost samples of a timed run with every task on one variant (0 hub, 1 wavefront):
+    (features float[count,5], log2(1 + wave-cycles) float[count])."""
     import torch
     lib = load()
     _cost_model_sigs(lib)
     X = torch.empty(max(capacity, 1) * MLP_IN, dtype=torch.float32, device=g.device)
     Y = torch.empty(max(capacity, 1), dtype=torch.float32, device=g.device)
     count = ctypes.c_int32()
-    _check(lib.ktruss_collect_row_costs(ctypes.byref(g.c), K, _ptr(X), _ptr(Y), capacity, ctypes.byref(count),
-                                        _stream(stream)))
+    _check(lib.ktruss_collect_row_costs(ctypes.byref(g.c), K, variant, _ptr(X), _ptr(Y), capacity,
+                                        ctypes.byref(count), _stream(stream)))
     c = count.value
     return X[: c * MLP_IN].view(c, MLP_IN), Y[:c]
 

@@ -104,3 +104,31 @@ def test_incremental_rejects_bad_modes():
         kt().ktruss_set_schedule(g, 0, None, t)
         with pytest.raises(kt().KtrussError):
             kt().ktruss_run(g, 3)
+
+
+@pytest.mark.parametrize("schedule", [0, 1, 4])
+@pytest.mark.parametrize("inc,ratio,rps", [(1, 0, 0), (2, 1, 0), (1, 0, 4)])
+def test_incremental_batched(schedule, inc, ratio, rps):
+    """The batched form with incremental maintenance: graphs that finish leave
+    the working set without destroying triangles; every graph's mask,
+    supports and pass count equal the oracle's."""
+    import torch
+    from test_gpu_batched import mixed_graphs
+    graphs, K = mixed_graphs(60, 17)
+    b = kt().Batch(graphs, device="cuda", schedule=schedule)
+    t = kt().ktruss_tuning()
+    t.incremental = inc
+    t.peel_ratio = ratio
+    t.rounds_per_sync = rps
+    b.c.tuning = t
+    print("case incremental batched G=%d m_total=%d schedule=%d mode=%d ratio=%d rps=%d"
+          % (b.G, b.m_total, schedule, inc, ratio, rps), flush=True)
+    mask, sup, rounds = kt().ktruss_run_batched(b, K)
+    torch.cuda.synchronize()
+    mask, sup, rounds = mask.cpu().numpy(), sup.cpu().numpy(), rounds.cpu().numpy()
+    eo = b.edge_offsets()
+    for g, (rp, col) in enumerate(graphs):
+        om, osup, orounds = oracle.truss(rp, col, int(K[g]), "P")
+        assert np.array_equal(mask[eo[g]:eo[g + 1]], om), g
+        assert np.array_equal(sup[eo[g]:eo[g + 1]], osup), g
+        assert rounds[g] == orounds, (g, rounds[g], orounds)

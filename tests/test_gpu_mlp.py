@@ -94,14 +94,15 @@ def test_learned_schedule_never_changes_results(kind, rmat12):
     t = kt().ktruss_tuning()
     if kind == "all-hub":
         theta[:] = 0
-        theta[-1] = 40.0            # predicts 2^40 cycles everywhere: every row is a hub row, split finely
+        theta[-1] = -40.0           # hub predicted 2^40 times cheaper everywhere: every row is a hub row
     elif kind == "no-hub":
         theta[:] = 0
-        theta[-1] = -40.0           # nothing is a hub row: all tasks on wave/thread kernels
+        theta[-1] = 40.0            # nothing is a hub row: all tasks on wave/thread kernels
     elif kind == "nan":
         theta[:] = np.nan
     elif kind == "tiny-chunks":
-        t.hub_chunk_work = 1
+        theta[-1] = -1.0
+        t.hub_chunk_tasks = 16
         t.learned_hub_min = 0.5
     params = dev(theta)
     for K in (3, 4, 6, 9):
@@ -115,7 +116,7 @@ def test_learned_schedule_skewed_graph():
     n, s, d = synth.rmat(15, 16, 0.65, 0.15, 0.15, 71)
     rp, col, _ = kt().ktruss_build_csr(s, d, n)
     theta = np.random.default_rng(3).normal(0, 0.5, ref.N_PARAMS).astype(np.float32)
-    theta[-1] = 14.0
+    theta[-1] = 0.0                 # a mix of hub and per-edge rows
     for K in (3, 7):
         gm, gs, gr = learned_run(rp, col, K, dev(theta))
         om, osup, orounds = oracle.truss(rp, col, K, "P")
@@ -128,8 +129,36 @@ def test_cost_samples_and_training_beat_constant():
     graphs = [(13, 0.5, 1), (14, 0.6, 2), (15, 0.57, 3)]
     X, Y = cost_model.collect(graphs, Ks=(3, 5, 8), per_run_cap=200_000, log=lambda *a: None)
     assert X.shape[0] > 1000 and X.shape[1] == 5
-    assert torch.isfinite(X).all() and torch.isfinite(Y).all() and (Y > 0).all()
+    assert torch.isfinite(X).all() and torch.isfinite(Y).all()
     params, hist = cost_model.train(X, Y, steps=600, batch=8192, lr=3e-3, log=lambda *a: None, eval_every=300)
-    step, train_mse, val_mse, const_mse = hist[-1]
-    print("cost model: held-out mse %.4f vs constant predictor %.4f" % (val_mse, const_mse), flush=True)
-    assert val_mse < 0.5 * const_mse
+    step, train_mse, val_mse, const_mse, sign = hist[-1]
+    print("cost model: held-out mse %.4f vs constant predictor %.4f, sign agreement %.3f"
+          % (val_mse, const_mse, sign), flush=True)
+    assert val_mse < 0.8 * const_mse
+
+
+def test_trained_model_gains_on_measured_costs():
+    """On a graph outside the training set, the per-row costs measured on both
+    kernels (paired samples) are summed under three policies: every row on the
+    hub kernel, every row on the wavefront kernel, and the trained network's
+    choice (hub where it predicts the hub kernel cheaper).  The network's
+    choice must cost less than either fixed policy; the gain is printed."""
+    import torch
+    from paper_2009_07929_amd import cost_model
+    params = cost_model.load_params("cuda")
+    assert params is not None, "the trained cost-model weights ship with the package"
+    n, s, d = synth.rmat(17, 16, 0.62, 0.165, 0.165, 909)
+    rp, col, _ = kt().ktruss_build_csr(s, d, n)
+    g = kt().Graph(rp, col, device="cuda")
+    Xh, Yh = kt().ktruss_collect_row_costs(g, 5, 2_000_000, variant=cost_model.HUB)
+    Xw, Yw = kt().ktruss_collect_row_costs(g, 5, 2_000_000, variant=cost_model.WAVE)
+    assert len(Yh) == len(Yw) and torch.equal(Xh, Xw)
+    hub = torch.exp2(Yh.double()) - 1
+    wave = torch.exp2(Yw.double()) - 1
+    pred = kt().ktruss_mlp_forward(params, Xh)
+    choice = torch.where(pred <= 0, hub, wave)
+    c_hub, c_wave, c_net, c_best = (float(v.sum()) for v in (hub, wave, choice, torch.minimum(hub, wave)))
+    print("measured wave-cycles: all hub %.3e, all wavefront %.3e, network %.3e (best per row %.3e); "
+          "gain %.3fx over all-hub, %.3fx over all-wavefront" % (c_hub, c_wave, c_net, c_best, c_hub / c_net,
+                                                                 c_wave / c_net), flush=True)
+    assert c_net < c_hub and c_net < c_wave
