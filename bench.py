@@ -50,8 +50,8 @@ def recorded_traffic(workload, schedule):
     """Per-launch HBM bytes of the support kernel from the rocprofv3 counter runs
     recorded in profiles/traffic.json (FETCH_SIZE and WRITE_SIZE, scaled by the
     copy-kernel calibration); None if none was recorded for this workload and
-    schedule, or if the kernel's sources (its file and the shared header)
-    changed since."""
+    schedule (which name the run: e.g. "rmat-s23-ef16-clique600/hub/inc2"), or
+    if the kernel's sources (its file and the shared header) changed since."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -245,7 +245,7 @@ def sweep(args, kt, torch, workload, Ks, steps, warmup, rounds_per_sync):
     if hub and hub["launches"] == launches:
         kernel, avg_launch_ms = "k_support_hub", hub["ms"] / hub["launches"]
         bytes_per_launch = hub_bytes / launches
-        traffic = recorded_traffic(workload, args.schedule)
+        traffic = recorded_traffic(workload, "%s/inc%d" % (args.schedule, args.incremental))
     else:
         kernel, avg_launch_ms, traffic = "support pass", avg_pass_ms, None
         bytes_per_launch = mm_bytes / max(launches, 1)
@@ -337,6 +337,9 @@ def batched_leg(args, kt, torch, count):
         if key in autotune.load_cache():
             cfg = autotune.tuned_config(key)
             autotune.apply(b, cfg)
+    if cfg is None:
+        b.c.tuning.incremental = args.incremental
+        b.c.tuning.peel_ratio = args.peel_ratio
     K_d = torch.from_numpy(Kg).cuda()
     mask = torch.empty(b.m_total, dtype=torch.uint8, device="cuda:0")
     sup = torch.empty(b.m_total, dtype=torch.int32, device="cuda:0")
@@ -357,7 +360,8 @@ def batched_leg(args, kt, torch, count):
     out = {"workload": "chunglu-batch-%d" % count, "graphs": count, "edges": msum,
            "batched_edges_per_s": msum / t_batch, "batched_ms": t_batch * 1e3,
            "max_rounds": int(batch_rounds.max()),
-           "schedule": cfg["schedule"] if cfg else args.schedule, "autotuned": cfg}
+           "schedule": cfg["schedule"] if cfg else args.schedule, "autotuned": cfg,
+           "incremental": int(b.c.tuning.incremental), "peel_ratio": float(b.c.tuning.peel_ratio)}
     if args.no_per_graph:
         del b, mask, sup
         return out
@@ -635,10 +639,11 @@ def main():
     ap.add_argument("--workload", default="rmat-s23-ef16-clique600")
     ap.add_argument("--ks", default=None, help="comma-separated K values (default: the workload's)")
     ap.add_argument("--schedule", default="hub", choices=sorted(SCHEDULES))
-    ap.add_argument("--incremental", type=int, default=0, choices=(0, 1, 2),
+    ap.add_argument("--incremental", type=int, default=2, choices=(0, 1, 2),
                     help="support maintenance of the main legs: 0 recompute every pass, 1 peel after every prune, "
                          "2 peel unless a prune removes more than --peel-ratio x the survivors")
-    ap.add_argument("--peel-ratio", type=int, default=0)
+    ap.add_argument("--peel-ratio", type=float, default=0.0,
+                    help="incremental 2: peel unless a prune removes more than this x the survivors (0: 1.0)")
     ap.add_argument("--rounds-per-sync", type=int, default=0,
                     help="prune rounds replayed from a hipGraph per host check (<= 1: host loop)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

@@ -2,9 +2,10 @@
 
 Searches, by timed runs on the device, the schedule (hub, heuristic, learned,
 plain) and the knobs of ktruss_tuning: tasks per hub item, the hub-row
-threshold of the heuristic, the wavefront/thread cut-off, the learned split
-target, the light-graph gate and the number of prune rounds replayed from a
-hipGraph per host check.  Results are
+threshold of the heuristic, the wavefront/thread cut-off, the learned
+threshold, the light-graph gate, the number of prune rounds replayed from a
+hipGraph per host check, and recompute vs incremental support maintenance
+(with its peel ratio).  Results are
 keyed by (graph class, K) and cached in a JSON file; a cached entry is reused
 for any graph of the same class.  Every candidate produces identical results
 (the schedule never changes the truss), so only time is compared.
@@ -27,7 +28,8 @@ SCHEDULE_IDS = {"plain": kt.SCHED_PLAIN, "heuristic": kt.SCHED_HEURISTIC, "learn
                 "hub": kt.SCHED_FORCE_HUB}
 
 DEFAULT = {"schedule": "hub", "hub_chunk_tasks": 256, "hub_min_work": 8, "wave_min_work": 192,
-           "hub_chunk_work": 0, "learned_hub_min": 0.0, "rounds_per_sync": 0, "plain_max_work": 0}
+           "hub_chunk_work": 0, "learned_hub_min": 0.0, "rounds_per_sync": 0, "plain_max_work": 0,
+           "incremental": 2, "peel_ratio": 1.0}
 
 # values tried per knob (coordinate search, in this order)
 SPACE = [
@@ -38,6 +40,8 @@ SPACE = [
     ("wave_min_work", [64, 192, 768]),
     ("learned_hub_min", [-0.5, 0.0, 0.5]),
     ("plain_max_work", [-1, 0, 128]),
+    ("incremental", [0, 1, 2]),
+    ("peel_ratio", [0.25, 1.0, 4.0]),
 ]
 # knobs that only matter under some schedules
 RELEVANT = {"hub_min_work": {"heuristic"}, "wave_min_work": {"heuristic", "learned"},
@@ -67,6 +71,8 @@ def to_tuning(cfg) -> kt.ktruss_tuning:
     t.learned_hub_min = float(cfg["learned_hub_min"])
     t.rounds_per_sync = int(cfg["rounds_per_sync"])
     t.plain_max_work = int(cfg.get("plain_max_work", 0))
+    t.incremental = int(cfg.get("incremental", 0))   # entries cached before incremental maintenance: recompute
+    t.peel_ratio = float(cfg.get("peel_ratio", 0.0))
     return t
 
 
@@ -113,6 +119,8 @@ def search(target, run, mlp_params=None, reps=3, sweeps=1, log=None):
     for _ in range(sweeps):
         for knob, values in space:
             if knob in RELEVANT and best["schedule"] not in RELEVANT[knob]:
+                continue
+            if knob == "peel_ratio" and best["incremental"] != 2:
                 continue
             for v in values:
                 if v == best[knob]:
@@ -174,3 +182,21 @@ def tune_batch(b, K_dev, reps=3, path=CACHE, log=None):
     best, t, _ = search(b, lambda: kt.ktruss_run_batched(b, K_dev, mask, sup, rounds), None, reps=reps, log=log)
     store(key, best, t, path)
     return key, best, t
+
+
+if __name__ == "__main__":
+    # python -m paper_2009_07929_amd.autotune batch [cache path]: tunes the
+    # 4,096-graph batched workload on the GPU and stores its entry.
+    import sys
+    import torch
+    sys.path.insert(0, os.path.dirname(HERE))
+    import synth
+    if sys.argv[1:2] != ["batch"]:
+        raise SystemExit("usage: python -m paper_2009_07929_amd.autotune batch [cache path]")
+    path = sys.argv[2] if len(sys.argv) > 2 else CACHE
+    p = synth.WORKLOADS["chunglu-batch-4096"].params
+    gs = synth.batch_graphs(p["count"], p["seed"], p["nmin"], p["nmax"])
+    K = torch.from_numpy(np.array([x[3] for x in gs], np.int32)).cuda()
+    b = kt.Batch(kt.build_csrs([(n, s, d) for n, s, d, _ in gs]), device="cuda")
+    del gs
+    print(tune_batch(b, K, path=path, log=print))

@@ -188,7 +188,7 @@ int32_t check_graph(const ktruss_graph* g, bool need_work) {
     if (!g->rowptr || (g->m > 0 && !g->col)) return fail(KTRUSS_E_INVALID, "graph rowptr/col is null");
     rc = check_schedule(g->schedule);
     if (rc != KTRUSS_OK) return rc;
-    if (g->tuning.incremental < 0 || g->tuning.incremental > 2 || g->tuning.peel_ratio < 0)
+    if (g->tuning.incremental < 0 || g->tuning.incremental > 2 || !(g->tuning.peel_ratio >= 0.f))
         return fail(KTRUSS_E_INVALID, "tuning.incremental must be 0, 1 or 2 and peel_ratio >= 0");
     if (need_work) return check_work(g->work, g->work_bytes, (int64_t)full_layout(g->n, g->m, 0).L.total);
     return KTRUSS_OK;
@@ -435,7 +435,7 @@ bool csc_needed(const RunSpec& r) { return uses_csc(r.sched) || r.incremental !=
 PeelSpec peel_of(const RunSpec& r) {
     PeelSpec pk{};
     pk.on = r.incremental != 0;
-    pk.ratio = r.incremental == 2 ? (r.tuning.peel_ratio > 0 ? r.tuning.peel_ratio : 1) : 0;
+    pk.ratio = r.incremental == 2 ? (r.tuning.peel_ratio > 0.f ? r.tuning.peel_ratio : 1.f) : 0.f;
     return pk;
 }
 
@@ -534,15 +534,16 @@ int32_t run_rounds(const RunSpec& r, Work& w, hipStream_t s, Ctl& h) {
     RunSpec rg = r;
     if (r.incremental) {
         // the first pass computes the supports on the host loop; the captured
-        // rounds only prune and peel (always: a recomputation cannot be
-        // decided inside the graph)
+        // rounds only prune and peel.  Every prune peels, the first one too: a
+        // skipped peel would need a recomputation, which cannot be decided
+        // inside the graph (mode 2 runs as mode 1 here)
+        rg.incremental = 1;
         const PassDims d1{m_hint, h.n_items, h.n_wave, h.n_thread};
-        rc = enqueue_round(r, w, 0, d1, s, true);
+        rc = enqueue_round(rg, w, 0, d1, s, true);
         if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
         if (rc != KTRUSS_OK || h.done) return rc;
         m_hint = h.m_buf[1];
         p = 1;
-        rg.incremental = 1;
     }
     // hipGraph mode: two rounds (p -> 1-p -> p) captured once with upper-bound
     // grids, replayed ceil(rps / 2) times between host checks.
@@ -865,6 +866,8 @@ int32_t ktruss_run_batched(const ktruss_batch* b, const int32_t* K, uint8_t* mas
     if (rc != KTRUSS_OK) return rc;
     rc = check_schedule(b->schedule);
     if (rc != KTRUSS_OK) return rc;
+    if (b->tuning.incremental < 0 || b->tuning.incremental > 2 || !(b->tuning.peel_ratio >= 0.f))
+        return fail(KTRUSS_E_INVALID, "tuning.incremental must be 0, 1 or 2 and peel_ratio >= 0");
     if (!b->vert_off || !b->rowptr || (b->m_total > 0 && !b->col)) return fail(KTRUSS_E_INVALID, "batch arrays are null");
     if (b->G > 0 && (!K || !rounds)) return fail(KTRUSS_E_INVALID, "K/rounds is null");
     if (b->G == 0 && b->n_total > 0) return fail(KTRUSS_E_INVALID, "vertices but no graphs");

@@ -32,6 +32,18 @@ __device__ __forceinline__ void wave_common(int32_t a0, int32_t a1, VA va, EA ea
                                             EB eb, H hit) {
     if (a0 >= a1 || b0 >= b1) return;
     const int lane = __lane_id();
+    if (a1 - a0 <= 64 && b1 - b0 <= 64) {
+        // both lists fit one element per lane: B's elements are broadcast to
+        // every lane in turn and compared with the lane's element of A
+        const int32_t la = a1 - a0, lb = b1 - b0;
+        const int32_t va_l = lane < la ? va(a0 + lane) : -1;
+        const int32_t vb_l = lane < lb ? vb(b0 + lane) : -2;
+        for (int32_t j = 0; j < lb; ++j) {
+            const int32_t y = __shfl(vb_l, j);
+            if (lane < la && va_l == y) hit(ea(a0 + lane), eb(b0 + j));
+        }
+        return;
+    }
     const bool walk_a = a1 - a0 <= b1 - b0;
     const int32_t w0 = walk_a ? a0 : b0, w1 = walk_a ? a1 : b1;
     const int32_t s0 = walk_a ? b0 : a0, s1 = walk_a ? b1 : a1;
@@ -64,12 +76,12 @@ __device__ __forceinline__ int32_t in_lower(const int32_t* __restrict__ csrc, in
 
 __global__ __launch_bounds__(kBlock) void k_peel(Buf x, Buf y, Csc c, const int32_t* __restrict__ xscan,
                                                const int32_t* __restrict__ frontier, Ctl* ctl, int p,
-                                               int32_t ratio) {
+                                               float ratio) {
     if (ctl->done) return;
     const int32_t nf = ctl->m_buf[p] - ctl->kept;  // edges removed by this prune
     // auto mode: a frontier larger than ratio x the survivors is left to a
     // recomputation (the next round runs a support pass instead)
-    if (ratio > 0 && (int64_t)nf > (int64_t)ratio * ctl->kept) {
+    if (ratio > 0.f && (double)nf > (double)ratio * (double)ctl->kept) {
         if (blockIdx.x == 0 && threadIdx.x == 0) ctl->need_support = 1;
         return;
     }
@@ -121,7 +133,7 @@ __global__ void k_need_support_clear(Ctl* ctl) {
 }  // namespace
 
 hipError_t launch_peel(const Buf& x, const Buf& y, const Csc& c, const int32_t* xscan, const int32_t* frontier,
-                       Ctl* ctl, int p, int32_t ratio, int32_t m_hint, hipStream_t s) {
+                       Ctl* ctl, int p, float ratio, int32_t m_hint, hipStream_t s) {
     if (m_hint <= 0) return hipSuccess;
     k_need_support_clear<<<1, 64, 0, s>>>(ctl);
     const unsigned grid = min(grid_for((int64_t)m_hint * 64), (unsigned)kStreamMaxGrid);

@@ -32,7 +32,7 @@ class ktruss_tuning(ctypes.Structure):
     _fields_ = [("wave_min_work", ctypes.c_int32), ("hub_min_work", ctypes.c_int32),
                 ("hub_chunk_work", ctypes.c_int32), ("rounds_per_sync", ctypes.c_int32),
                 ("learned_hub_min", ctypes.c_float), ("hub_chunk_tasks", ctypes.c_int32),
-                ("plain_max_work", ctypes.c_int32), ("incremental", ctypes.c_int32), ("peel_ratio", ctypes.c_int32)]
+                ("plain_max_work", ctypes.c_int32), ("incremental", ctypes.c_int32), ("peel_ratio", ctypes.c_float)]
 
 
 MLP_IN, MLP_HIDDEN, MLP_PARAMS = 5, 64, 4609

@@ -23,6 +23,10 @@ def test_to_tuning_fields():
     assert autotune.to_tuning(dict(cfg, plain_max_work=128)).plain_max_work == 128
     old = {k: v for k, v in cfg.items() if k != "plain_max_work"}   # entries cached before the gate existed
     assert autotune.to_tuning(old).plain_max_work == 0
+    older = {k: v for k, v in old.items() if k not in ("incremental", "peel_ratio")}
+    assert autotune.to_tuning(older).incremental == 0    # entries cached before incremental maintenance
+    t = autotune.to_tuning(dict(cfg, incremental=2, peel_ratio=0.25))
+    assert t.incremental == 2 and abs(t.peel_ratio - 0.25) < 1e-7
 
 
 def test_cache_roundtrip(tmp_path):

@@ -153,6 +153,7 @@ def test_autotuner_picks_a_bit_exact_config(tmp_path, rmat12):
     graphs, K = mixed_graphs(20, 9)
     b = kt().Batch(graphs, device="cuda")
     key, best, t = autotune.tune_batch(b, torch.from_numpy(K).cuda(), reps=1, path=path)
+    print("case autotuned batch config %s" % best, flush=True)
     mask, sup, rounds = kt().ktruss_run_batched(b, K)
     torch.cuda.synchronize()
     eo = b.edge_offsets()

@@ -4,14 +4,18 @@ Every full-size workload is compared bit for bit with the oracle through
 digests the oracle wrote (tests/golden/digests.json, made by
 tests/golden/make_digests.py from oracle/ only; mode P from the full graph for
 every K, hours of CPU time at scale 23):
-* R-MAT scale 20 (15.7M edges), K = 3, 5, 8, 12, under every schedule;
+* R-MAT scale 20 (15.7M edges), K = 3, 5, 8, 12, under every schedule and
+  the hub schedule with incremental maintenance (the benchmark's setting);
 * R-MAT scale 23 + planted 600-clique (111.4M edges), K = 3, 10, 50, 600,
-  under the hub, heuristic and learned schedules;
+  under the hub schedule with incremental maintenance, and the hub, heuristic
+  and learned schedules recomputing;
 * R-MAT scale 22 (61.6M edges) and Barabasi-Albert n = 4M, m = 8 (33.6M
-  edges), K = 3, 6, 10, under the plain, heuristic, learned and hub schedules;
+  edges), K = 3, 6, 10, under the plain, heuristic, learned and hub schedules
+  and the hub schedule with incremental maintenance;
 * the 4,096 Chung-Lu graphs of the batched workload (222M edges, K per graph)
-  in one batched run: per-graph pass counts, truss sizes and support sums, and
-  digests of every graph's mask and supports.
+  in one batched run (autotuned; hub; hub with the persistent per-graph peel):
+  per-graph pass counts, truss sizes and support sums, and digests of every
+  graph's mask and supports.
 The scale-23 graph is also checked through properties that hold at any size
 (sampled supports recounted inside the returned truss, the K = 3 closed form,
 nesting, the planted clique surviving K = 600).
@@ -80,10 +84,15 @@ def check_workload(name, csr, schedules, keyed_below=20_000_000):
     assert gold["m"] == len(col) and gold["n"] == len(rp) - 1
     g = kt().Graph(rp, col, device="cuda")
     for schedule in schedules:
-        kt().ktruss_set_schedule(g, schedule, mlp_params() if schedule == 2 else None)
+        # an int is a schedule with default tuning; "4i" is the hub schedule with
+        # incremental maintenance (mode 2), the benchmark's configuration
+        t = kt().ktruss_tuning()
+        if schedule == "4i":
+            schedule, t.incremental = 4, 2
+        kt().ktruss_set_schedule(g, schedule, mlp_params() if schedule == 2 else None, t)
         for Ks, want in sorted(gold["K"].items(), key=lambda kv: int(kv[0])):
             K = int(Ks)
-            print("case %s K=%d schedule=%d" % (name, K, schedule), flush=True)
+            print("case %s K=%d schedule=%d incremental=%d" % (name, K, schedule, t.incremental), flush=True)
             mask, sup, rounds = kt().ktruss_run(g, K)
             torch.cuda.synchronize()
             mask, sup = mask.cpu().numpy(), sup.cpu().numpy()
@@ -98,7 +107,7 @@ def check_workload(name, csr, schedules, keyed_below=20_000_000):
     del g
 
 
-@pytest.mark.parametrize("schedule", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("schedule", [0, 1, 2, 3, 4, 5, "4i"])
 def test_rmat20_digests(schedule, s20):
     check_workload("rmat-s20-ef16", s20, [schedule])
 
@@ -113,7 +122,7 @@ def built(name):
 def test_rmat23_clique_digests():
     if "rmat-s23-ef16-clique600" not in GOLDEN:
         pytest.skip("no golden digests for rmat-s23-ef16-clique600")
-    check_workload("rmat-s23-ef16-clique600", built("rmat-s23-ef16-clique600"), [4, 1, 2])
+    check_workload("rmat-s23-ef16-clique600", built("rmat-s23-ef16-clique600"), ["4i", 4, 1, 2])
 
 
 @pytest.mark.slow
@@ -122,12 +131,12 @@ def test_rmat23_clique_digests():
 def test_evaluation_graph_digests(name):
     if name not in GOLDEN:
         pytest.skip("no golden digests for %s" % name)
-    check_workload(name, built(name), [0, 1, 2, 4])
+    check_workload(name, built(name), [0, 1, 2, 4, "4i"])
 
 
 @pytest.mark.slow
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("schedule", ["autotuned", 4])
+@pytest.mark.parametrize("schedule", ["autotuned", 4, "hub-incremental"])
 def test_batch_digests(schedule):
     """The whole batched workload in one ktruss_run_batched call."""
     import torch
@@ -141,7 +150,11 @@ def test_batch_digests(schedule):
     assert K.tolist() == gold["K"]
     csr = kt().build_csrs([(n, s, d) for n, s, d, _ in gs])
     del gs
-    b = kt().Batch(csr, device="cuda", schedule=4 if schedule == 4 else 1)
+    b = kt().Batch(csr, device="cuda", schedule=1 if schedule == "autotuned" else 4)
+    if schedule == "hub-incremental":   # one support pass, then every graph's peel in one persistent launch
+        t = kt().ktruss_tuning()
+        t.incremental = 2
+        b.c.tuning = t
     if schedule == "autotuned":
         from paper_2009_07929_amd import autotune
         key = autotune.batch_class(b.G, b.m_total)

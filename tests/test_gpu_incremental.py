@@ -57,8 +57,8 @@ def test_incremental_matches_oracle(idx):
     for K in (3, 4, 6, 9, 14):
         om, osup, orounds = oracle.truss(rp, col, K, "P")
         for sched in (0, 1, 4, 5):
-            for inc, ratio, rps in ((1, 0, 0), (2, 1, 0), (2, 4, 0), (1, 0, 3)):
-                print("case incremental %s m=%d K=%d schedule=%d mode=%d ratio=%d rps=%d"
+            for inc, ratio, rps in ((1, 0, 0), (2, 1, 0), (2, 4, 0), (2, 0.25, 0), (1, 0, 3), (2, 0.25, 4)):
+                print("case incremental %s m=%d K=%d schedule=%d mode=%d ratio=%g rps=%d"
                       % (name, len(col), K, sched, inc, ratio, rps), flush=True)
                 mask, sup, rounds = run(rp, col, K, sched, inc, ratio, rps)
                 assert rounds == orounds, (K, sched, inc, rounds, orounds)
@@ -97,7 +97,7 @@ def test_incremental_rejects_bad_modes():
     n, s, d = synth.complete(5)
     rp, col, _ = kt().ktruss_build_csr(s, d, n)
     g = kt().Graph(rp, col, device="cuda")
-    for inc, ratio in ((3, 0), (-1, 0), (2, -1)):
+    for inc, ratio in ((3, 0), (-1, 0), (2, -1.0), (2, float("nan"))):
         t = kt().ktruss_tuning()
         t.incremental = inc
         t.peel_ratio = ratio
@@ -106,29 +106,34 @@ def test_incremental_rejects_bad_modes():
             kt().ktruss_run(g, 3)
 
 
+@pytest.mark.parametrize("seed,count", [(17, 60), (9, 20)])
 @pytest.mark.parametrize("schedule", [0, 1, 4])
-@pytest.mark.parametrize("inc,ratio,rps", [(1, 0, 0), (2, 1, 0), (1, 0, 4)])
-def test_incremental_batched(schedule, inc, ratio, rps):
-    """The batched form with incremental maintenance: graphs that finish leave
-    the working set without destroying triangles; every graph's mask,
-    supports and pass count equal the oracle's."""
+@pytest.mark.parametrize("inc,ratio,rps", [(0, 0, 4), (0, 0, 16), (1, 0, 0), (1, 0, 4), (1, 0, 16), (2, 1, 0),
+                                           (2, 0.25, 0), (2, 4, 0), (2, 0.25, 16)])
+def test_incremental_batched(schedule, inc, ratio, rps, seed, count):
+    """The batched form with incremental maintenance (and, for reference,
+    recomputing with graph-replayed rounds): graphs that finish leave the
+    working set without destroying triangles; every graph's mask, supports
+    and pass count equal the oracle's."""
     import torch
     from test_gpu_batched import mixed_graphs
-    graphs, K = mixed_graphs(60, 17)
+    graphs, K = mixed_graphs(count, seed)
     b = kt().Batch(graphs, device="cuda", schedule=schedule)
     t = kt().ktruss_tuning()
     t.incremental = inc
     t.peel_ratio = ratio
     t.rounds_per_sync = rps
     b.c.tuning = t
-    print("case incremental batched G=%d m_total=%d schedule=%d mode=%d ratio=%d rps=%d"
+    print("case incremental batched G=%d m_total=%d schedule=%d mode=%d ratio=%g rps=%d"
           % (b.G, b.m_total, schedule, inc, ratio, rps), flush=True)
     mask, sup, rounds = kt().ktruss_run_batched(b, K)
     torch.cuda.synchronize()
     mask, sup, rounds = mask.cpu().numpy(), sup.cpu().numpy(), rounds.cpu().numpy()
     eo = b.edge_offsets()
+    bad = []
     for g, (rp, col) in enumerate(graphs):
         om, osup, orounds = oracle.truss(rp, col, int(K[g]), "P")
-        assert np.array_equal(mask[eo[g]:eo[g + 1]], om), g
-        assert np.array_equal(sup[eo[g]:eo[g + 1]], osup), g
-        assert rounds[g] == orounds, (g, rounds[g], orounds)
+        if not (np.array_equal(mask[eo[g]:eo[g + 1]], om) and np.array_equal(sup[eo[g]:eo[g + 1]], osup)
+                and rounds[g] == orounds):
+            bad.append((g, int(K[g]), len(col), int(rounds[g]), orounds))
+    assert not bad, bad
