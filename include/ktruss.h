@@ -187,6 +187,25 @@ int32_t ktruss_prune(const ktruss_graph* g, int32_t K, const int32_t* support, u
 int32_t ktruss_run(const ktruss_graph* g, int32_t K, uint8_t* mask, int32_t* support,
                    int32_t* rounds, void* stream);
 
+/*
+ * ktruss_run_noalloc — for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Computes exactly what ktruss_run computes for the graph
+ * (n, m, rowptr, col: device, the CSR conventions above) under `schedule`
+ * (any but KTRUSS_SCHED_LEARNED) with default tuning and host-checked rounds,
+ * but its working memory is a fixed 64 MiB device array inside the library
+ * instead of a caller workspace: one copy per GPU, created when the library
+ * is loaded and held until the process ends; no allocation happens in the
+ * call.  Graphs whose ktruss_workspace_bytes(n, m, 0) exceeds 64 MiB (about
+ * 400k edges with 100k vertices) are rejected with KTRUSS_E_CAPACITY before
+ * any device work.  mask (device uint8[m]), support (device int32[m]) and
+ * rounds (host) as in ktruss_run; synchronises `stream`.  All calls on one
+ * GPU share that array: two calls that overlap on the same GPU (from two
+ * threads or two streams) race and must not be issued.  The array keeps the
+ * last call's contents; every call re-initialises what it reads.
+ */
+int32_t ktruss_run_noalloc(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* col, int32_t schedule,
+                           int32_t K, uint8_t* mask, int32_t* support, int32_t* rounds, void* stream);
 
 /*
  * ktruss_decompose — the trussness of every edge (the K_max analysis of

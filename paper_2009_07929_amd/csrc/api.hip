@@ -316,6 +316,33 @@ unsigned long long* profile_work() {
     return P.on ? P.work_dev : nullptr;
 }
 
+// Fixed workspace of ktruss_run_noalloc: a file-scope device array (one copy
+// per GPU, resident until the process ends), for callers that cannot
+// allocate.  Host code never passes the array's name to a kernel: it takes
+// the address hipGetSymbolAddress reports on each device, once per device.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+
+int32_t noalloc_scratch(void** out) {
+    static std::mutex mu;
+    static void* ptr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail_hip(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(KTRUSS_E_INVALID, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return fail_hip(e, "scratch address");
+        ptr[dev] = p;
+    }
+    *out = ptr[dev];
+    return KTRUSS_OK;
+}
+
 bool uses_csc(int sched) {
     return sched != KTRUSS_SCHED_PLAIN && sched != KTRUSS_SCHED_FORCE_WAVE && sched != KTRUSS_SCHED_COARSE;
 }
@@ -802,6 +829,33 @@ int32_t ktruss_run(const ktruss_graph* g, int32_t K, uint8_t* mask, int32_t* sup
     HIP_TRY(hipStreamSynchronize(s), "run sync");
     if (rounds) *rounds = h.rounds;
     return KTRUSS_OK;
+}
+
+int32_t ktruss_run_noalloc(int32_t n, int64_t m, const int32_t* rowptr, const int32_t* col, int32_t schedule,
+                           int32_t K, uint8_t* mask, int32_t* support, int32_t* rounds, void* stream) {
+    clear_error();
+    int32_t rc = check_sizes(n, m);
+    if (rc != KTRUSS_OK) return rc;
+    rc = check_schedule(schedule);
+    if (rc != KTRUSS_OK) return rc;
+    if (schedule == KTRUSS_SCHED_LEARNED) return fail(KTRUSS_E_INVALID, "the learned schedule needs its weights");
+    const int64_t need = (int64_t)full_layout(n, m, 0).L.total;
+    if (need > (int64_t)kNoAllocScratchBytes)
+        return fail(KTRUSS_E_CAPACITY, "graph needs %lld workspace bytes, the fixed scratch holds %lld",
+                    (long long)need, (long long)kNoAllocScratchBytes);
+    void* work = nullptr;
+    rc = noalloc_scratch(&work);
+    if (rc != KTRUSS_OK) return rc;
+    ktruss_graph g{};
+    g.n = n;
+    g.m = m;
+    g.schedule = schedule;
+    g.rowptr = rowptr;
+    g.col = col;
+    g.work = work;
+    g.work_bytes = (int64_t)kNoAllocScratchBytes;
+    // host-checked rounds (rounds_per_sync = 0): no graph to instantiate
+    return ktruss_run(&g, K, mask, support, rounds, stream);
 }
 
 int32_t ktruss_decompose(const ktruss_graph* g, int32_t* trussness, int32_t* k_max, void* stream) {

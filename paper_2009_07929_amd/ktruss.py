@@ -69,6 +69,7 @@ def load():
         "ktruss_support": ([G, p, p, p], i32),
         "ktruss_prune": ([G, i32, p, p, p, p], i32),
         "ktruss_run": ([G, i32, p, p, p, p], i32),
+        "ktruss_run_noalloc": ([i32, i64, p, p, i32, i32, p, p, p, p], i32),
         "ktruss_decompose": ([G, p, p, p], i32),
         "ktruss_set_schedule": ([G, i32, p, ctypes.POINTER(ktruss_tuning)], i32),
         "ktruss_profile_enable": ([i32], i32),
