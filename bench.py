@@ -600,7 +600,8 @@ def decompose_leg(args, kt, torch, wname="rmat-s20-ef16"):
     del s, d
     m = len(col)
     g = kt.Graph(rowptr, col, device="cuda:0")
-    kt.ktruss_set_schedule(g, SCHEDULES[args.schedule], None, tuning(kt, 0))
+    kt.ktruss_set_schedule(g, SCHEDULES[args.schedule], None,
+                           tuning(kt, 0, args.incremental, args.peel_ratio))
     stream = torch.cuda.current_stream()
     tr = torch.empty(m, dtype=torch.int32, device="cuda:0")
     kt.ktruss_decompose(g, tr, stream)  # warm-up
@@ -628,7 +629,8 @@ def decompose_leg(args, kt, torch, wname="rmat-s20-ef16"):
         raise RuntimeError("decomposition disagrees with the per-K runs on %s" % wname)
     del g
     return {"workload": wname, "m": m, "k_max": k_max, "decompose_ms": t_dec * 1e3, "edges_per_s": m / t_dec,
-            "per_K_runs_ms": t_each * 1e3, "speedup_vs_per_K_runs": t_each / t_dec, "agree": agree}
+            "per_K_runs_ms": t_each * 1e3, "speedup_vs_per_K_runs": t_each / t_dec, "agree": agree,
+            "incremental": args.incremental}
 
 
 def main():
@@ -643,7 +645,8 @@ def main():
                     help="support maintenance of the main legs: 0 recompute every pass, 1 peel after every prune, "
                          "2 peel unless a prune removes more than --peel-ratio x the survivors")
     ap.add_argument("--peel-ratio", type=float, default=0.0,
-                    help="incremental 2: peel unless a prune removes more than this x the survivors (0: 1.0)")
+                    help="incremental 2: peel unless a prune removes more than this x the survivors (0: the "
+                         "library default, 0.125)")
     ap.add_argument("--rounds-per-sync", type=int, default=0,
                     help="prune rounds replayed from a hipGraph per host check (<= 1: host loop)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

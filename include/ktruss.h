@@ -83,7 +83,7 @@ typedef struct ktruss_tuning {
                                 hipGraph (rounds_per_sync >= 2) use mode 1 for 2.  Also for ktruss_run_batched
                                 (the edges of a graph that finishes leave the working set without destroying
                                 triangles). */
-    float peel_ratio;        /* incremental = 2: the ratio above (0: 1.0) */
+    float peel_ratio;        /* incremental = 2: the ratio above (0: the default 0.125) */
 } ktruss_tuning;
 
 /* Cost model: 5 inputs -> 64 ReLU -> 64 ReLU -> 1 output, FP32.  Parameter

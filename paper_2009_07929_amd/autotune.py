@@ -29,7 +29,7 @@ SCHEDULE_IDS = {"plain": kt.SCHED_PLAIN, "heuristic": kt.SCHED_HEURISTIC, "learn
 
 DEFAULT = {"schedule": "hub", "hub_chunk_tasks": 256, "hub_min_work": 8, "wave_min_work": 192,
            "hub_chunk_work": 0, "learned_hub_min": 0.0, "rounds_per_sync": 0, "plain_max_work": 0,
-           "incremental": 2, "peel_ratio": 1.0}
+           "incremental": 2, "peel_ratio": 0.125}
 
 # values tried per knob (coordinate search, in this order)
 SPACE = [
@@ -41,7 +41,7 @@ SPACE = [
     ("learned_hub_min", [-0.5, 0.0, 0.5]),
     ("plain_max_work", [-1, 0, 128]),
     ("incremental", [0, 1, 2]),
-    ("peel_ratio", [0.25, 1.0, 4.0]),
+    ("peel_ratio", [0.03125, 0.125, 0.5, 2.0]),
 ]
 # knobs that only matter under some schedules
 RELEVANT = {"hub_min_work": {"heuristic"}, "wave_min_work": {"heuristic", "learned"},

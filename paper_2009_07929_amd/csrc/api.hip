@@ -462,7 +462,7 @@ bool csc_needed(const RunSpec& r) { return uses_csc(r.sched) || r.incremental !=
 PeelSpec peel_of(const RunSpec& r) {
     PeelSpec pk{};
     pk.on = r.incremental != 0;
-    pk.ratio = r.incremental == 2 ? (r.tuning.peel_ratio > 0.f ? r.tuning.peel_ratio : 1.f) : 0.f;
+    pk.ratio = r.incremental == 2 ? (r.tuning.peel_ratio > 0.f ? r.tuning.peel_ratio : kDefaultPeelRatio) : 0.f;
     return pk;
 }
 

@@ -37,6 +37,10 @@ constexpr int kHitWordsPerEdge = 8;      // hit-word capacity of the workspace p
 constexpr float kDefaultLearnedHubMax = 0.0f;
 constexpr int32_t kDefaultPlainMaxWork = 32;
 constexpr int kMinLearnedChunk = 16;     // fewest tasks per hub item
+// incremental maintenance, mode 2: a prune removing more than this fraction of
+// the edges it keeps is followed by a recomputation instead of a peel (measured
+// on R-MAT scales 20 and 23 over 0.125 .. 2: 0.125 was the fastest or tied)
+constexpr float kDefaultPeelRatio = 0.125f;
 // internal schedule of cost sampling: every task on the wavefront kernel,
 // through the binned path (in-edge lists, row features, per-row timing)
 constexpr int kSchedSampleWave = 100;

@@ -12,11 +12,11 @@
 // of the round's alive graph from the full neighbourhoods of u and v: the
 // out-row of a vertex holds its larger neighbours, its in-edge list (the
 // transpose, entries ordered by row) its smaller ones, both ascending.  The
-// third vertex w lies below u (in-list of u against in-list of v), between u
-// and v (out-row of u before f against in-list of v) or above v (out-row of
-// u after f, Algorithm 3's tail, against out-row of v).  One wave per removed
-// edge: the lanes walk the shorter list of each pair and binary-search the
-// longer one.
+// third vertex w lies below v (u's in-list followed by its out-row before f,
+// against v's in-list) or above v (u's out-row after f, Algorithm 3's tail,
+// against v's out-row).  One wave per removed edge: the lanes walk the shorter
+// list of each pair and binary-search the longer one, or, when both fit in 64
+// lanes, compare one list against the other held in registers.
 #include "device_util.h"
 #include "kernels.h"
 
@@ -69,11 +69,6 @@ __device__ __forceinline__ void wave_common(int32_t a0, int32_t a1, VA va, EA ea
     }
 }
 
-// First entry of in-edge list [c0, c1) whose row is >= r.
-__device__ __forceinline__ int32_t in_lower(const int32_t* __restrict__ csrc, int32_t c0, int32_t c1, int32_t r) {
-    return c0 + lower_bound_i32(csrc + c0, c1 - c0, r);
-}
-
 __global__ __launch_bounds__(kBlock) void k_peel(Buf x, Buf y, Csc c, const int32_t* __restrict__ xscan,
                                                const int32_t* __restrict__ frontier, Ctl* ctl, int p,
                                                float ratio) {
@@ -106,16 +101,18 @@ __global__ __launch_bounds__(kBlock) void k_peel(Buf x, Buf y, Csc c, const int3
         const int32_t rv0 = x.rowptr[v], rv1 = x.rowptr[v + 1];
         const int32_t cu0 = c.ptr[u], cu1 = c.ptr[u + 1];
         const int32_t cv0 = c.ptr[v], cv1 = c.ptr[v + 1];
-        const int32_t cvu = in_lower(csrc, cv0, cv1, u);  // in(v) entries of rows < u end here; f's entry follows
+        // w < v: u's neighbours below v, its in-list (w < u) followed by its
+        // out-row before f (u < w < v), all ascending, against v's in-list (every
+        // neighbour of v below v; u itself is not in the first list)
+        const int32_t nin = cu1 - cu0;
+        auto low_val = [&](int32_t q) { return q < nin ? csrc[cu0 + q] : col[ru0 + (q - nin)]; };
+        auto low_edge = [&](int32_t q) { return q < nin ? cedge[cu0 + q] : ru0 + (q - nin); };
         auto in_val = [&](int32_t q) { return csrc[q]; };
         auto in_edge = [&](int32_t q) { return cedge[q]; };
+        wave_common(0, nin + (f - ru0), low_val, low_edge, cv0, cv1, in_val, in_edge, charge);
+        // w > v: edges (u, w) and (v, w): u's tail after f against v's out-row
         auto row_val = [&](int32_t q) { return col[q]; };
         auto row_edge = [&](int32_t q) { return q; };
-        // w < u: edges (w, u) and (w, v)
-        wave_common(cu0, cu1, in_val, in_edge, cv0, cvu, in_val, in_edge, charge);
-        // u < w < v: edges (u, w) and (w, v)
-        wave_common(ru0, f, row_val, row_edge, min(cvu + 1, cv1), cv1, in_val, in_edge, charge);
-        // w > v: edges (u, w) and (v, w)
         wave_common(f + 1, ru1, row_val, row_edge, rv0, rv1, row_val, row_edge, charge);
     }
 }
