@@ -68,6 +68,7 @@ FullLayout full_layout(int32_t n, int64_t m, int32_t G) {
     L.ckey = take(em);
     L.cptr = take(vn);
     L.xscan = take(em1);
+    L.keepw = take(sizeof(KeepWord) * ((size_t)m / 64 + 1));
     L.cxscan = take(em1);
     L.blockcnt = take(sizeof(int32_t) * kMaxScanBlocks);
     L.blockoff = take(sizeof(int32_t) * kMaxScanBlocks);
@@ -127,6 +128,7 @@ Work carve(void* work, int32_t n, int64_t m, int32_t G) {
         w.c[b].ptr = (int32_t*)(base + L.cptr);
     }
     w.sc.xscan = (int32_t*)(base + L.xscan);
+    w.sc.keepw = (KeepWord*)(base + L.keepw);
     w.sc.cxscan = (int32_t*)(base + L.cxscan);
     w.sc.blockcnt = (int32_t*)(base + L.blockcnt);
     w.sc.blockoff = (int32_t*)(base + L.blockoff);

@@ -111,9 +111,20 @@ struct HubItem {
     int32_t k, c0, c1, rs, d, last, pad0, pad1;
 };
 
+// Keep flags of a compaction, 64 elements to a word, with the number of kept
+// elements before the word: element e's new position is pref plus the kept
+// bits below e's bit.  A 16-byte entry per 64 elements, so scattered lookups
+// of new positions hit a table 1/16 the size of a per-element one.
+struct alignas(16) KeepWord {
+    unsigned long long bits;
+    int32_t pref;
+    int32_t pad;
+};
+
 // Per-run scratch arrays inside the workspace.
 struct Scratch {
     int32_t* xscan;       // int32[m+1]: new CSR position of every old position
+    KeepWord* keepw;      // KeepWord[m/64 + 1]: the same as keep bits and per-word counts
     int32_t* cxscan;      // int32[m+1]: same for in-edge list entries when the lists are packed
     int32_t* blockcnt;    // int32[kMaxScanBlocks]
     int32_t* blockoff;    // int32[kMaxScanBlocks]
@@ -170,7 +181,7 @@ __host__ __device__ inline int64_t hit_words_upto(int32_t x) {
 struct Layout {
     size_t col[2], src[2], eid[2], S[2], rowptr[2];
     size_t cedge, csrc, ckey, cptr;
-    size_t xscan, cxscan, blockcnt, blockoff, blockcnt2, blockoff2, alive_in, itemoff, items, ctail,
+    size_t xscan, keepw, cxscan, blockcnt, blockoff, blockcnt2, blockoff2, alive_in, itemoff, items, ctail,
         is_hub, hub_row, hitw, hwoff, wave_tasks, thread_tasks, insum, cycles, act_off, act_list, feats, pred, chunk_sz,
         rs_hist;
     size_t ctl;        // Ctl

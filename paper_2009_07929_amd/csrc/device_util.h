@@ -5,6 +5,14 @@
 
 namespace kt {
 
+// New position q of element e (kept), or ~q (dropped, q kept elements before it).
+__device__ __forceinline__ int32_t keep_rank(const KeepWord* __restrict__ kw, int32_t e) {
+    const KeepWord k = kw[e >> 6];
+    const int b = e & 63;
+    const int32_t q = k.pref + __popcll(k.bits & ((1ull << b) - 1ull));
+    return ((k.bits >> b) & 1ull) ? q : ~q;
+}
+
 // Number of set bits of `mask` in lanes below the calling lane.
 __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));

@@ -74,9 +74,11 @@ struct CsrAlive {
 
 // ---- generic stable filter
 
+// Workgroup chunks of [0, N): multiples of kBlock, so that every wave's 64
+// elements form one keep word.
 __device__ __forceinline__ void chunk_of(int32_t N, int32_t& lo, int32_t& hi) {
     const int32_t G = (int32_t)gridDim.x;
-    const int32_t chunk = (int32_t)(((int64_t)N + G - 1) / G);
+    const int64_t chunk = (((int64_t)N + G - 1) / G + kBlock - 1) / kBlock * kBlock;
     lo = (int32_t)min((int64_t)blockIdx.x * chunk, (int64_t)N);
     hi = (int32_t)min((int64_t)lo + chunk, (int64_t)N);
 }
@@ -157,7 +159,7 @@ __global__ __launch_bounds__(kScanThreads) void k_filter_scan(const int32_t* __r
 template <class P>
 __global__ __launch_bounds__(kBlock) void k_filter_scatter(P pol, const Ctl* __restrict__ ctl, int p, int round,
                                                          const int32_t* __restrict__ blockoff,
-                                                         int32_t* __restrict__ xscan) {
+                                                         int32_t* __restrict__ xscan, KeepWord* __restrict__ keepw) {
     __shared__ int s_wave[kBlock / 64];
     if (round && ctl->done) return;
     int32_t lo, hi;
@@ -170,6 +172,8 @@ __global__ __launch_bounds__(kBlock) void k_filter_scatter(P pol, const Ctl* __r
         const bool k = in && pol.keep(v);
         int tot;
         const int32_t q = base + block_excl_flag<kBlock>(k, s_wave, tot);
+        const unsigned long long kb = __ballot(k);
+        if (__lane_id() == 0 && in) keepw[i >> 6] = KeepWord{kb, q, 0};  // i is the word's first element
         if (in) {
             xscan[i] = k ? q : ~q;  // new position; ~ marks a dropped element
             if (k) pol.emit(v, i, q);
@@ -198,13 +202,13 @@ __global__ __launch_bounds__(kBlock) void k_zero_rows(int32_t* __restrict__ a, i
 }
 
 // In-edge lists after the CSR filter, in place: every entry's edge position
-// becomes the edge's new position (xscan holds q for a kept edge, ~q for a
+// becomes the edge's new position (keep_rank: q for a kept edge, ~q for a
 // removed one); entries of removed edges, and tombstones, stay -1.  The alive
 // entries of every row kappa are counted on the way (alive_in, zeroed
 // before): the lists are grouped by kappa (key), so a wave-level segmented
 // sum adds each run and its last lane issues one atomic per run piece.
 __global__ __launch_bounds__(kBlock) void k_csc_remap(int32_t* __restrict__ cedge, const int32_t* __restrict__ ckey,
-                                                    const int32_t* __restrict__ xscan, int32_t* __restrict__ alive_in,
+                                                    const KeepWord* __restrict__ keepw, int32_t* __restrict__ alive_in,
                                                     const Ctl* __restrict__ ctl, int round) {
     if (round && ctl->done) return;
     const int32_t N = ctl->csc_m;
@@ -217,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_csc_remap(int32_t* __restrict__ cedg
         if (c < N) {
             const int32_t e = cedge[c];
             if (e >= 0) {
-                const int32_t q = xscan[e];
+                const int32_t q = keep_rank(keepw, e);
                 cedge[c] = q >= 0 ? q : -1;
                 v = q >= 0;
             }
@@ -344,11 +348,11 @@ int32_t filter_grid(int32_t m_hint) {
 
 template <class P>
 void run_filter(const P& pol, Ctl* ctl, int p, int update, int round, int32_t* blockcnt, int32_t* blockoff,
-                int32_t* xscan, int32_t m_hint, hipStream_t s) {
+                int32_t* xscan, KeepWord* keepw, int32_t m_hint, hipStream_t s) {
     const int32_t G = filter_grid(m_hint);
     k_filter_count<P><<<G, kBlock, 0, s>>>(pol, ctl, p, round, blockcnt);
     k_filter_scan<<<1, kScanThreads, 0, s>>>(blockcnt, blockoff, G, ctl, p, update, round, xscan);
-    k_filter_scatter<P><<<G, kBlock, 0, s>>>(pol, ctl, p, round, blockoff, xscan);
+    k_filter_scatter<P><<<G, kBlock, 0, s>>>(pol, ctl, p, round, blockoff, xscan, keepw);
 }
 
 }  // namespace
@@ -361,18 +365,18 @@ hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* 
     const bool inc = peel.on && mode == 0 && cx;
     if (mode == 0) {
         run_filter(CsrRound{x, y, thr, b, inc ? sc.thread_tasks : nullptr}, ctl, p, batch ? 3 : 1, 1, sc.blockcnt,
-                   sc.blockoff, sc.xscan, m_hint, s);
+                   sc.blockoff, sc.xscan, sc.keepw, m_hint, s);
     } else {
-        run_filter(CsrAlive{x, y, alive_can}, ctl, p, 2, 0, sc.blockcnt, sc.blockoff, sc.xscan, m_hint, s);
+        run_filter(CsrAlive{x, y, alive_can}, ctl, p, 2, 0, sc.blockcnt, sc.blockoff, sc.xscan, sc.keepw, m_hint, s);
     }
     k_ptr_remap<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(x.rowptr, y.rowptr, n, sc.xscan, ctl, round);
     if (inc) {  // on the round's graph: buffer p's rows and the in-edge lists before their remap
-        const hipError_t e = launch_peel(x, y, *cx, sc.xscan, sc.thread_tasks, ctl, p, peel.ratio, m_hint, s);
+        const hipError_t e = launch_peel(x, y, *cx, sc.keepw, sc.thread_tasks, ctl, p, peel.ratio, m_hint, s);
         if (e != hipSuccess) return e;
     }
     if (cx && csc_hint > 0) {  // the in-edge lists (one set: cy names the same arrays) and alive in-edge counts
         k_zero_rows<<<grid_for(n), kBlock, 0, s>>>(sc.alive_in, n, ctl, round);
-        k_csc_remap<<<min(grid_for(csc_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(cx->edge, cx->key, sc.xscan,
+        k_csc_remap<<<min(grid_for(csc_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(cx->edge, cx->key, sc.keepw,
                                                                                          sc.alive_in, ctl, round);
         // packing when tombstones dominate; scratch that the next preparation rebuilds holds the packed copy
         const Csc t{sc.wave_tasks, sc.thread_tasks, sc.ctail, sc.itemoff};

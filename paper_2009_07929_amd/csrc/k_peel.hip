@@ -69,7 +69,7 @@ __device__ __forceinline__ void wave_common(int32_t a0, int32_t a1, VA va, EA ea
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_peel(Buf x, Buf y, Csc c, const int32_t* __restrict__ xscan,
+__global__ __launch_bounds__(kBlock) void k_peel(Buf x, Buf y, Csc c, const KeepWord* __restrict__ keepw,
                                                const int32_t* __restrict__ frontier, Ctl* ctl, int p,
                                                float ratio) {
     if (ctl->done) return;
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_peel(Buf x, Buf y, Csc c, const int3
         // smaller position is in it; decrement its surviving edges
         auto charge = [&](int32_t e1, int32_t e2) {
             if (e1 < 0 || e2 < 0) return;  // an edge removed in an earlier round: not a triangle of this round
-            const int32_t q1 = xscan[e1], q2 = xscan[e2];
+            const int32_t q1 = keep_rank(keepw, e1), q2 = keep_rank(keepw, e2);
             if ((q1 < 0 && e1 < f) || (q2 < 0 && e2 < f)) return;
             if (q1 >= 0) atomicSub(&y.S[q1], 1);
             if (q2 >= 0) atomicSub(&y.S[q2], 1);
@@ -129,12 +129,12 @@ __global__ void k_need_support_clear(Ctl* ctl) {
 
 }  // namespace
 
-hipError_t launch_peel(const Buf& x, const Buf& y, const Csc& c, const int32_t* xscan, const int32_t* frontier,
+hipError_t launch_peel(const Buf& x, const Buf& y, const Csc& c, const KeepWord* keepw, const int32_t* frontier,
                        Ctl* ctl, int p, float ratio, int32_t m_hint, hipStream_t s) {
     if (m_hint <= 0) return hipSuccess;
     k_need_support_clear<<<1, 64, 0, s>>>(ctl);
     const unsigned grid = min(grid_for((int64_t)m_hint * 64), (unsigned)kStreamMaxGrid);
-    k_peel<<<grid, kBlock, 0, s>>>(x, y, c, xscan, frontier, ctl, p, ratio);
+    k_peel<<<grid, kBlock, 0, s>>>(x, y, c, keepw, frontier, ctl, p, ratio);
     return hipGetLastError();
 }
 

@@ -193,10 +193,11 @@ struct RowWords {
 //
 // 8-bit digits.  Per pass: every workgroup histograms the digits of its tile
 // of kRsTile pairs (LDS counters); the digit-major table of those histograms is
-// scanned; then every workgroup scatters its tile in order, ranking equal
-// digits within each wave by eight ballots (one per digit bit) and across
-// waves and sub-rounds through LDS counts.  Stable, so every column's list
-// stays in ascending edge order; no global atomics.
+// scanned; then every workgroup ranks its tile in order (equal digits within
+// a wave by eight ballots, one per digit bit, and across sub-rounds and waves
+// through LDS counts), reorders it by digit in LDS and writes each digit's
+// run out contiguously.  Stable, so every column's list stays in ascending
+// edge order; no global atomics.
 
 constexpr int kRsItems = kRsTile / kBlock;
 
@@ -216,22 +217,38 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const int32_t* __restrict__ 
 }
 
 // vals == nullptr: the values are the positions themselves (first pass).
+// Every wave ranks a contiguous quarter of the tile (16 sub-rounds of 64
+// pairs) against its own LDS digit counters; the tile is then reordered by
+// digit in LDS and written out, so that each digit's run of the tile leaves
+// as consecutive stores rather than one scattered store per pair.
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(const int32_t* __restrict__ keys, const int32_t* __restrict__ vals,
                                                      int32_t N, int shift, int32_t nblk, const int32_t* __restrict__ off,
                                                      int32_t* __restrict__ keys_out, int32_t* __restrict__ vals_out) {
-    __shared__ int s_run[256];
-    __shared__ int s_wcnt[kBlock / 64][256];
-    const int t = threadIdx.x, w = t >> 6;
-    s_run[t] = 0;
+    constexpr int kWaves = kBlock / 64;
+    constexpr int kPerWave = kRsTile / kWaves;
+    __shared__ int32_t s_k[kRsTile];
+    __shared__ int32_t s_v[kRsTile];
+    __shared__ int s_cnt[kWaves][256];  // per-wave digit counts, then each wave's offset within its digit
+    __shared__ int s_loc[256];          // first tile-local slot of every digit
+    __shared__ int s_glob[256];         // first output position of every digit's run of this tile
+    __shared__ int s_ws[kWaves];
+    const int t = threadIdx.x, w = t >> 6, lane = __lane_id();
 #pragma unroll
-    for (int i = 0; i < kBlock / 64; ++i) s_wcnt[i][t] = 0;
+    for (int i = 0; i < kWaves; ++i) s_cnt[i][t] = 0;
+    s_glob[t] = off[(int64_t)t * nblk + blockIdx.x];
     __syncthreads();
-    const int32_t base = (int32_t)blockIdx.x * kRsTile;
-    const uint64_t lt = (1ull << __lane_id()) - 1ull;
+    const int32_t tile0 = (int32_t)blockIdx.x * kRsTile;
+    const int32_t base = tile0 + w * kPerWave;
+    const uint64_t lt = (1ull << lane) - 1ull;
+    int32_t kreg[kRsItems], vreg[kRsItems];
+    int rank[kRsItems];
+#pragma unroll
     for (int j = 0; j < kRsItems; ++j) {
-        const int32_t e = base + j * kBlock + t;
+        const int32_t e = base + j * 64 + lane;
         const bool valid = e < N;
         const int32_t key = valid ? keys[e] : 0;
+        kreg[j] = key;
+        vreg[j] = valid ? (vals ? vals[e] : e) : 0;
         const int d = (key >> shift) & 255;
         uint64_t match = __ballot(valid);
 #pragma unroll
@@ -239,25 +256,50 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const int32_t* __restrict
             const uint64_t bb = __ballot(valid && ((d >> b) & 1));
             match &= ((d >> b) & 1) ? bb : ~bb;
         }
-        const int rank = __popcll(match & lt);
-        if (valid && rank == 0) s_wcnt[w][d] = __popcll(match);
-        __syncthreads();
-        if (valid) {
-            int pre = s_run[d];
-            for (int i = 0; i < w; ++i) pre += s_wcnt[i][d];
-            const int32_t pos = off[(int64_t)d * nblk + blockIdx.x] + pre + rank;
-            keys_out[pos] = key;
-            vals_out[pos] = vals ? vals[e] : e;
-        }
-        __syncthreads();
-        int add = 0;
+        const int r = __popcll(match & lt);
+        const int before = s_cnt[w][d];
+        __builtin_amdgcn_wave_barrier();  // every lane has read the count before its leader advances it
+        if (valid && r == 0) s_cnt[w][d] = before + __popcll(match);
+        __builtin_amdgcn_wave_barrier();
+        rank[j] = valid ? before + r : -1;
+    }
+    __syncthreads();
+    // digit t: per-wave offsets and the tile-local start (exclusive scan over digits)
+    int tot = 0;
 #pragma unroll
-        for (int i = 0; i < kBlock / 64; ++i) {
-            add += s_wcnt[i][t];
-            s_wcnt[i][t] = 0;
-        }
-        s_run[t] += add;
-        __syncthreads();
+    for (int i = 0; i < kWaves; ++i) {
+        const int c = s_cnt[i][t];
+        s_cnt[i][t] = tot;
+        tot += c;
+    }
+    int incl = tot;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(incl, o);
+        if (lane >= o) incl += u;
+    }
+    if (lane == 63) s_ws[w] = incl;
+    __syncthreads();
+    int wpre = 0;
+    for (int i = 0; i < w; ++i) wpre += s_ws[i];
+    s_loc[t] = wpre + incl - tot;
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kRsItems; ++j) {
+        if (rank[j] < 0) continue;
+        const int d = (kreg[j] >> shift) & 255;
+        const int l = s_loc[d] + s_cnt[w][d] + rank[j];
+        s_k[l] = kreg[j];
+        s_v[l] = vreg[j];
+    }
+    __syncthreads();
+    const int32_t nvalid = min((int32_t)kRsTile, N - tile0);
+    for (int i = t; i < nvalid; i += kBlock) {
+        const int32_t key = s_k[i];
+        const int d = (key >> shift) & 255;
+        const int32_t pos = s_glob[d] + (i - s_loc[d]);
+        keys_out[pos] = key;
+        vals_out[pos] = s_v[i];
     }
 }
 

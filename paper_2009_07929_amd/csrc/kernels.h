@@ -43,7 +43,7 @@ hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* 
                           const uint8_t* alive_can, const BatchCtx& b, Scratch& sc, Ctl* ctl, int p, int32_t m_hint,
                           int32_t csc_hint, const PeelSpec& peel, hipStream_t s);
 // The peel itself (k_peel.hip), on buffer x's graph, survivors' supports in y.
-hipError_t launch_peel(const Buf& x, const Buf& y, const Csc& c, const int32_t* xscan, const int32_t* frontier,
+hipError_t launch_peel(const Buf& x, const Buf& y, const Csc& c, const KeepWord* keepw, const int32_t* frontier,
                        Ctl* ctl, int p, float ratio, int32_t m_hint, hipStream_t s);
 // Zeroes the supports of buffer p's alive edges (a recomputation follows a
 // round whose compaction kept them).
