@@ -545,6 +545,78 @@ hipStream_t capture_stream(hipError_t& e) {
     return cs;
 }
 
+// In-place rounds: incremental maintenance of one graph (not sampling costs).
+bool in_place(const RunSpec& r) { return r.incremental != 0 && r.G == 0 && !r.collect; }
+
+// In-place rounds replayed from a hipGraph, two per replay, ceil(rps / 2)
+// replays between host checks; every round peels (mode 1), so the buffer
+// never changes.
+int32_t state_rounds_graph(const RunSpec& r, Work& w, int p, int32_t m_hint, Ctl& h, hipStream_t s) {
+    hipError_t e;
+    hipStream_t cs = capture_stream(e);
+    if (e != hipSuccess) return fail_hip(e, "capture stream");
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
+    t_capturing = true;
+    e = launch_state_round(w.b[p], w.c[p], r.thr, w.sc.thread_tasks, w.sc, w.ctl, p, 0.f, m_hint, cs);
+    if (e == hipSuccess) e = launch_state_round(w.b[p], w.c[p], r.thr, w.sc.thread_tasks, w.sc, w.ctl, p, 0.f, m_hint, cs);
+    t_capturing = false;
+    hipError_t ec = hipStreamEndCapture(cs, &graph);
+    if (e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return fail_hip(e, "in-place round capture");
+    }
+    if (ec != hipSuccess) return fail_hip(ec, "end capture");
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail_hip(e, "graph instantiate");
+    }
+    const int replays = (r.tuning.rounds_per_sync + 1) / 2;
+    int32_t rc = KTRUSS_OK;
+    for (;;) {
+        for (int i = 0; i < replays && rc == KTRUSS_OK; ++i) {
+            e = hipGraphLaunch(exec, s);
+            if (e != hipSuccess) rc = fail_hip(e, "graph launch");
+        }
+        if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
+        if (rc != KTRUSS_OK || h.done) break;
+    }
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return rc;
+}
+
+// In-place rounds from buffer p, whose alive edges hold current supports,
+// until the fixpoint (Ctl::final_buf, Ctl::kept: the buffer and its alive
+// count).  Each round marks the removed edges in S, counts and peels them
+// without moving anything, so the in-edge lists keep their positions.  A
+// round whose frontier exceeds ratio x the survivors (mode 2) compacts the
+// survivors into the other buffer instead and recomputes their supports
+// there.
+int32_t state_rounds(const RunSpec& r, Work& w, int p, int32_t m_hint, Ctl& h, hipStream_t s) {
+    if (r.tuning.rounds_per_sync >= 2) return state_rounds_graph(r, w, p, m_hint, h, s);
+    const float ratio = peel_of(r).ratio;
+    for (;;) {
+        HIP_TRY(launch_state_round(w.b[p], w.c[p], r.thr, w.sc.thread_tasks, w.sc, w.ctl, p, ratio, m_hint, s),
+                "in-place round");
+        int32_t rc = read_ctl(w, h, s);
+        if (rc != KTRUSS_OK || h.done) return rc;
+        if (!h.need_support) continue;
+        HIP_TRY(launch_compact(w.b[p], w.b[1 - p], &w.c[p], &w.c[1 - p], r.n, 2, r.thr, nullptr, w.batch, w.sc, w.ctl,
+                               p, m_hint, r.m, PeelSpec{}, s),
+                "survivor compaction");
+        p ^= 1;
+        rc = prepare(r, w, p, m_hint, s);
+        if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
+        if (rc != KTRUSS_OK) return rc;
+        m_hint = h.m_buf[p];
+        rc = support_pass(r.sched, r.n, w, p, PassDims{m_hint, h.n_items, h.n_wave, h.n_thread}, s);
+        if (rc != KTRUSS_OK) return rc;
+    }
+}
+
 // Runs rounds from buffer 0 until the fixpoint.  The work before the first
 // round (set-up, in-edge lists, first preparation) is already enqueued on s.
 int32_t run_rounds(const RunSpec& r, Work& w, hipStream_t s, Ctl& h) {
@@ -555,6 +627,10 @@ int32_t run_rounds(const RunSpec& r, Work& w, hipStream_t s, Ctl& h) {
         if (rc != KTRUSS_OK) return rc;
     } else {
         h.m_buf[0] = r.m;
+    }
+    if (in_place(r)) {  // the first support pass, then in-place rounds
+        rc = support_pass(r.sched, r.n, w, 0, PassDims{r.m, h.n_items, h.n_wave, h.n_thread}, s);
+        return rc == KTRUSS_OK ? state_rounds(r, w, 0, r.m, h, s) : rc;
     }
     const int rps = r.tuning.rounds_per_sync;
     if (rps <= 1) return host_rounds(r, w, 0, r.m, true, h, s);
@@ -884,10 +960,11 @@ int32_t ktruss_decompose(const ktruss_graph* g, int32_t* trussness, int32_t* k_m
     Ctl h{};
     if (rc == KTRUSS_OK) rc = run_rounds(r, w, s, h);
     if (rc != KTRUSS_OK) return rc;
+    const bool inplace = in_place(r);
     for (int32_t K = 3;; ++K) {
         const int f = h.final_buf;
         const int32_t mf = h.m_buf[f];
-        if (mf == 0) {
+        if ((inplace ? h.kept : mf) == 0) {
             *k_max = K - 1;
             break;
         }
@@ -896,6 +973,11 @@ int32_t ktruss_decompose(const ktruss_graph* g, int32_t* trussness, int32_t* k_m
         // threshold (their supports are exact), then rounds until the fixpoint
         r.thr = K - 1;
         HIP_TRY(launch_ctl_restart(w.ctl, s), "level restart");
+        if (inplace) {
+            rc = state_rounds(r, w, f, mf, h, s);
+            if (rc != KTRUSS_OK) return rc;
+            continue;
+        }
         const bool csc = csc_needed(r);
         HIP_TRY(launch_compact(w.b[f], w.b[1 - f], csc ? &w.c[f] : nullptr, csc ? &w.c[1 - f] : nullptr, r.n, 0, r.thr,
                                nullptr, w.batch, w.sc, w.ctl, f, mf, r.m, peel_of(r), s),

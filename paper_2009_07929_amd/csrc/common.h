@@ -60,6 +60,11 @@ enum PassStat {
 
 // Device-resident control block of one run.  Buffer b of the double-buffered
 // working graph holds m_buf[b] alive edges.
+// Support values of edges that in-place rounds have removed (alive edges
+// hold their support, >= 0).
+constexpr int32_t kDead = -1;   // removed by an earlier round
+constexpr int32_t kDying = -2;  // removed by the current round
+
 struct Ctl {
     int32_t m_buf[2];
     int32_t done;        // a pass removed nothing: later kernels of the run do no work
@@ -77,7 +82,7 @@ struct Ctl {
     int32_t csc_pack;    // the lists are being packed in this round (tombstones dominate)
     int32_t csc_next;    // entries after packing
     int32_t need_support; // incremental maintenance skipped its peel: the next round recomputes supports
-    int32_t pad_;
+    int32_t front_n;      // edges removed by the current in-place prune (incremental maintenance)
     int64_t removed_total;
     unsigned long long merge_work;  // input's merge length summed over its edges (row tail + row kappa)
 };

@@ -331,6 +331,55 @@ __global__ void k_csc_pack_end(Ctl* ctl) {
     }
 }
 
+// ---- marking of an in-place round: the same count / scan / scatter as the
+// filter, writing only the removed edges' positions (in position order) and
+// their marks.
+__device__ __forceinline__ bool state_dying(int32_t d, int32_t thr) { return d >= 0 && d < thr; }
+
+__global__ __launch_bounds__(kBlock) void k_state_count(Buf x, const Ctl* __restrict__ ctl, int p, int32_t thr,
+                                                      int32_t* __restrict__ blockcnt) {
+    __shared__ int s_wave[kBlock / 64];
+    if (ctl->done) return;
+    int32_t lo, hi;
+    chunk_of(ctl->m_buf[p], lo, hi);
+    int c = 0;
+    for (int32_t i = lo + (int32_t)threadIdx.x; i < hi; i += kBlock) c += state_dying(x.S[i], thr);
+    c = block_sum<kBlock>(c, s_wave);
+    if (threadIdx.x == 0) blockcnt[blockIdx.x] = c;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_state_scan(const int32_t* __restrict__ blockcnt,
+                                                           int32_t* __restrict__ blockoff, int32_t G, Ctl* ctl) {
+    __shared__ int s_wave[kScanThreads / 64];
+    if (ctl->done) return;
+    const int total = scan_block_counts(blockcnt, blockoff, G, s_wave);
+    if (threadIdx.x == 0) ctl->front_n = total;
+}
+
+__global__ __launch_bounds__(kBlock) void k_state_scatter(Buf x, const Ctl* __restrict__ ctl, int p, int32_t thr,
+                                                        const int32_t* __restrict__ blockoff,
+                                                        int32_t* __restrict__ frontier) {
+    __shared__ int s_wave[kBlock / 64];
+    if (ctl->done) return;
+    int32_t lo, hi;
+    chunk_of(ctl->m_buf[p], lo, hi);
+    int32_t base = blockoff[blockIdx.x];
+    for (int32_t t0 = lo; t0 < hi; t0 += kBlock) {
+        const int32_t i = t0 + (int32_t)threadIdx.x;
+        const int32_t d = i < hi ? x.S[i] : kDead;
+        const bool k = state_dying(d, thr);
+        int tot;
+        const int32_t q = base + block_excl_flag<kBlock>(k, s_wave, tot);
+        if (k) {
+            x.S[i] = kDying;
+            frontier[q] = i;
+        } else if (d == kDying) {
+            x.S[i] = kDead;
+        }
+        base += tot;
+    }
+}
+
 // Batched form: the run ends after the pass that leaves no edge.
 __global__ void k_batch_end(Ctl* ctl, int p) {
     if (threadIdx.x == 0 && !ctl->done && ctl->m_buf[1 - p] == 0) {
@@ -357,15 +406,27 @@ void run_filter(const P& pol, Ctl* ctl, int p, int update, int round, int32_t* b
 
 }  // namespace
 
+hipError_t launch_state_mark(const Buf& x, int32_t thr, int32_t* frontier, Scratch& sc, Ctl* ctl, int p,
+                             int32_t m_hint, hipStream_t s) {
+    const int32_t G = filter_grid(m_hint);
+    k_state_count<<<G, kBlock, 0, s>>>(x, ctl, p, thr, sc.blockcnt);
+    k_state_scan<<<1, kScanThreads, 0, s>>>(sc.blockcnt, sc.blockoff, G, ctl);
+    k_state_scatter<<<G, kBlock, 0, s>>>(x, ctl, p, thr, sc.blockoff, frontier);
+    return hipGetLastError();
+}
+
 hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* cy, int32_t n, int mode, int32_t thr,
                           const uint8_t* alive_can, const BatchCtx& b, Scratch& sc, Ctl* ctl, int p, int32_t m_hint,
                           int32_t csc_hint, const PeelSpec& peel, hipStream_t s) {
-    const int round = mode == 0;
+    const int round = mode != 1;
     const bool batch = b.thrv != nullptr;
     const bool inc = peel.on && mode == 0 && cx;
     if (mode == 0) {
         run_filter(CsrRound{x, y, thr, b, inc ? sc.thread_tasks : nullptr}, ctl, p, batch ? 3 : 1, 1, sc.blockcnt,
                    sc.blockoff, sc.xscan, sc.keepw, m_hint, s);
+    } else if (mode == 2) {
+        run_filter(CsrRound{x, y, thr, b, nullptr}, ctl, p, 2, 1, sc.blockcnt, sc.blockoff, sc.xscan, sc.keepw,
+                   m_hint, s);
     } else {
         run_filter(CsrAlive{x, y, alive_can}, ctl, p, 2, 0, sc.blockcnt, sc.blockoff, sc.xscan, sc.keepw, m_hint, s);
     }

@@ -69,6 +69,35 @@ __device__ __forceinline__ void wave_common(int32_t a0, int32_t a1, VA va, EA ea
     }
 }
 
+// Every triangle (f, e1, e2) of removed edge f = (u, v) in the lists of x and
+// c is passed to charge(e1, e2) (entries of removed edges included: the
+// charge rule tells them apart).  One wave.
+template <class Charge>
+__device__ __forceinline__ void peel_triangles(const Buf& x, const Csc& c, int32_t f, Charge charge) {
+    const int32_t* __restrict__ col = x.col;
+    const int32_t* __restrict__ csrc = c.src;
+    const int32_t* __restrict__ cedge = c.edge;
+    const int32_t u = x.src[f], v = col[f];
+    const int32_t ru0 = x.rowptr[u], ru1 = x.rowptr[u + 1];
+    const int32_t rv0 = x.rowptr[v], rv1 = x.rowptr[v + 1];
+    const int32_t cu0 = c.ptr[u], cu1 = c.ptr[u + 1];
+    const int32_t cv0 = c.ptr[v], cv1 = c.ptr[v + 1];
+    // w < v: u's neighbours below v, its in-list (w < u) followed by its
+    // out-row before f (u < w < v), all ascending, against v's in-list (every
+    // neighbour of v below v; u itself is not in the first list)
+    const int32_t nin = cu1 - cu0;
+    auto low_val = [&](int32_t q) { return q < nin ? csrc[cu0 + q] : col[ru0 + (q - nin)]; };
+    auto low_edge = [&](int32_t q) { return q < nin ? cedge[cu0 + q] : ru0 + (q - nin); };
+    auto in_val = [&](int32_t q) { return csrc[q]; };
+    auto in_edge = [&](int32_t q) { return cedge[q]; };
+    wave_common(0, nin + (f - ru0), low_val, low_edge, cv0, cv1, in_val, in_edge, charge);
+    // w > v: edges (u, w) and (v, w): u's tail after f against v's out-row
+    auto row_val = [&](int32_t q) { return col[q]; };
+    auto row_edge = [&](int32_t q) { return q; };
+    wave_common(f + 1, ru1, row_val, row_edge, rv0, rv1, row_val, row_edge, charge);
+}
+
+// Peel after a compaction: x is the round's graph, y the compacted survivors.
 __global__ __launch_bounds__(kBlock) void k_peel(Buf x, Buf y, Csc c, const KeepWord* __restrict__ keepw,
                                                const int32_t* __restrict__ frontier, Ctl* ctl, int p,
                                                float ratio) {
@@ -80,14 +109,10 @@ __global__ __launch_bounds__(kBlock) void k_peel(Buf x, Buf y, Csc c, const Keep
         if (blockIdx.x == 0 && threadIdx.x == 0) ctl->need_support = 1;
         return;
     }
-    const int32_t* __restrict__ col = x.col;
-    const int32_t* __restrict__ csrc = c.src;
-    const int32_t* __restrict__ cedge = c.edge;
     const int32_t nw = (int32_t)(gridDim.x * (kBlock / 64));
     for (int32_t wid = (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 6); wid < nf; wid += nw) {
         const int32_t f = frontier[wid];
         if (f < 0) continue;  // an edge of a finished graph (batched form): its triangles stay
-        const int32_t u = x.src[f], v = col[f];
         // charge the triangle (f, e1, e2) here unless a removed edge with a
         // smaller position is in it; decrement its surviving edges
         auto charge = [&](int32_t e1, int32_t e2) {
@@ -97,23 +122,52 @@ __global__ __launch_bounds__(kBlock) void k_peel(Buf x, Buf y, Csc c, const Keep
             if (q1 >= 0) atomicSub(&y.S[q1], 1);
             if (q2 >= 0) atomicSub(&y.S[q2], 1);
         };
-        const int32_t ru0 = x.rowptr[u], ru1 = x.rowptr[u + 1];
-        const int32_t rv0 = x.rowptr[v], rv1 = x.rowptr[v + 1];
-        const int32_t cu0 = c.ptr[u], cu1 = c.ptr[u + 1];
-        const int32_t cv0 = c.ptr[v], cv1 = c.ptr[v + 1];
-        // w < v: u's neighbours below v, its in-list (w < u) followed by its
-        // out-row before f (u < w < v), all ascending, against v's in-list (every
-        // neighbour of v below v; u itself is not in the first list)
-        const int32_t nin = cu1 - cu0;
-        auto low_val = [&](int32_t q) { return q < nin ? csrc[cu0 + q] : col[ru0 + (q - nin)]; };
-        auto low_edge = [&](int32_t q) { return q < nin ? cedge[cu0 + q] : ru0 + (q - nin); };
-        auto in_val = [&](int32_t q) { return csrc[q]; };
-        auto in_edge = [&](int32_t q) { return cedge[q]; };
-        wave_common(0, nin + (f - ru0), low_val, low_edge, cv0, cv1, in_val, in_edge, charge);
-        // w > v: edges (u, w) and (v, w): u's tail after f against v's out-row
-        auto row_val = [&](int32_t q) { return col[q]; };
-        auto row_edge = [&](int32_t q) { return q; };
-        wave_common(f + 1, ru1, row_val, row_edge, rv0, rv1, row_val, row_edge, charge);
+        peel_triangles(x, c, f, charge);
+    }
+}
+
+// ---- in-place rounds.  Between compactions the edges keep their positions
+// and their state lives in S: a support (>= 0) for an alive edge, kDying for
+// an edge removed by the current round's prune, kDead for one removed by an
+// earlier round.  A round marks the removed edges and lists them, decides,
+// and peels; nothing is moved, so the in-edge lists need no remap.
+
+// One thread: the round's bookkeeping (pass count, fixpoint, survivors) and,
+// with ratio > 0, whether the frontier is left to a recomputation.
+__global__ void k_state_decide(Ctl* ctl, int p, float ratio) {
+    if (threadIdx.x != 0 || blockIdx.x != 0 || ctl->done) return;
+    const int32_t nf = ctl->front_n;
+    ctl->rounds += 1;
+    ctl->need_support = 0;
+    if (nf == 0) {
+        ctl->done = 1;
+        ctl->final_buf = p;
+        return;
+    }
+    ctl->kept -= nf;
+    ctl->removed_total += nf;
+    if (ratio > 0.f && (double)nf > (double)ratio * (double)ctl->kept) ctl->need_support = 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_peel_state(Buf x, Csc c, const int32_t* __restrict__ frontier,
+                                                     const Ctl* __restrict__ ctl) {
+    if (ctl->done || ctl->need_support) return;
+    const int32_t nf = ctl->front_n;
+    int32_t* __restrict__ S = x.S;
+    const int32_t nw = (int32_t)(gridDim.x * (kBlock / 64));
+    for (int32_t wid = (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 6); wid < nf; wid += nw) {
+        const int32_t f = frontier[wid];
+        // a survivor's S stays >= 0 throughout (it loses at most the triangles
+        // it closes), so kDying and kDead read the same while others decrement
+        auto charge = [&](int32_t e1, int32_t e2) {
+            if (e1 < 0 || e2 < 0) return;  // tombstones of the in-lists: removed before the last compaction
+            const int32_t s1 = S[e1], s2 = S[e2];
+            if (s1 == kDead || s2 == kDead) return;  // not a triangle of this round
+            if ((s1 == kDying && e1 < f) || (s2 == kDying && e2 < f)) return;
+            if (s1 != kDying) atomicSub(&S[e1], 1);
+            if (s2 != kDying) atomicSub(&S[e2], 1);
+        };
+        peel_triangles(x, c, f, charge);
     }
 }
 
@@ -128,6 +182,19 @@ __global__ void k_need_support_clear(Ctl* ctl) {
 }
 
 }  // namespace
+
+hipError_t launch_state_round(const Buf& x, const Csc& c, int32_t thr, int32_t* frontier, Scratch& sc, Ctl* ctl,
+                              int p, float ratio, int32_t m_hint, hipStream_t s) {
+    // an empty buffer still takes the round's bookkeeping (it ends the run)
+    const hipError_t e = launch_state_mark(x, thr, frontier, sc, ctl, p, m_hint, s);
+    if (e != hipSuccess) return e;
+    k_state_decide<<<1, 64, 0, s>>>(ctl, p, ratio);
+    if (m_hint > 0) {
+        const unsigned grid = min(grid_for((int64_t)m_hint * 64), (unsigned)kStreamMaxGrid);
+        k_peel_state<<<grid, kBlock, 0, s>>>(x, c, frontier, ctl);
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_peel(const Buf& x, const Buf& y, const Csc& c, const KeepWord* keepw, const int32_t* frontier,
                        Ctl* ctl, int p, float ratio, int32_t m_hint, hipStream_t s) {

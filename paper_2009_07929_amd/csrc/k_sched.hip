@@ -221,13 +221,19 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const int32_t* __restrict__ 
 // pairs) against its own LDS digit counters; the tile is then reordered by
 // digit in LDS and written out, so that each digit's run of the tile leaves
 // as consecutive stores rather than one scattered store per pair.
+// kRow: a second value (the edge's row) travels with every pair, read from
+// rows (indexed like vals) and written to rows_out.
+template <bool kRow>
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(const int32_t* __restrict__ keys, const int32_t* __restrict__ vals,
-                                                     int32_t N, int shift, int32_t nblk, const int32_t* __restrict__ off,
-                                                     int32_t* __restrict__ keys_out, int32_t* __restrict__ vals_out) {
+                                                     const int32_t* __restrict__ rows, int32_t N, int shift,
+                                                     int32_t nblk, const int32_t* __restrict__ off,
+                                                     int32_t* __restrict__ keys_out, int32_t* __restrict__ vals_out,
+                                                     int32_t* __restrict__ rows_out) {
     constexpr int kWaves = kBlock / 64;
     constexpr int kPerWave = kRsTile / kWaves;
     __shared__ int32_t s_k[kRsTile];
     __shared__ int32_t s_v[kRsTile];
+    __shared__ int32_t s_w[kRow ? kRsTile : 1];
     __shared__ int s_cnt[kWaves][256];  // per-wave digit counts, then each wave's offset within its digit
     __shared__ int s_loc[256];          // first tile-local slot of every digit
     __shared__ int s_glob[256];         // first output position of every digit's run of this tile
@@ -240,7 +246,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const int32_t* __restrict
     const int32_t tile0 = (int32_t)blockIdx.x * kRsTile;
     const int32_t base = tile0 + w * kPerWave;
     const uint64_t lt = (1ull << lane) - 1ull;
-    int32_t kreg[kRsItems], vreg[kRsItems];
+    int32_t kreg[kRsItems], vreg[kRsItems], rreg[kRow ? kRsItems : 1];
     int rank[kRsItems];
 #pragma unroll
     for (int j = 0; j < kRsItems; ++j) {
@@ -249,6 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const int32_t* __restrict
         const int32_t key = valid ? keys[e] : 0;
         kreg[j] = key;
         vreg[j] = valid ? (vals ? vals[e] : e) : 0;
+        if constexpr (kRow) rreg[j] = valid ? rows[e] : 0;
         const int d = (key >> shift) & 255;
         uint64_t match = __ballot(valid);
 #pragma unroll
@@ -291,6 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const int32_t* __restrict
         const int l = s_loc[d] + s_cnt[w][d] + rank[j];
         s_k[l] = kreg[j];
         s_v[l] = vreg[j];
+        if constexpr (kRow) s_w[l] = rreg[j];
     }
     __syncthreads();
     const int32_t nvalid = min((int32_t)kRsTile, N - tile0);
@@ -300,6 +308,7 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const int32_t* __restrict
         const int32_t pos = s_glob[d] + (i - s_loc[d]);
         keys_out[pos] = key;
         vals_out[pos] = s_v[i];
+        if constexpr (kRow) rows_out[pos] = s_w[i];
     }
 }
 
@@ -309,13 +318,6 @@ __global__ __launch_bounds__(kBlock) void k_col_ptr(const int32_t* __restrict__ 
     const int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (k > n) return;
     cptr[k] = lower_bound_i32(sorted, m, (int32_t)k);
-}
-
-// Row of every in-edge list entry (the edge's row i).
-__global__ __launch_bounds__(kBlock) void k_csc_rows(const int32_t* __restrict__ src, const int32_t* __restrict__ edge,
-                                                   int32_t m, int32_t* __restrict__ csrc) {
-    const int64_t q = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (q < m) csrc[q] = src[edge[q]];
 }
 
 // Tail length of the task of every in-edge list entry of the pass: the part
@@ -619,10 +621,12 @@ __global__ __launch_bounds__(kBlock) void k_task_scatter(TaskClass tc, const Ctl
 // order, vals_out the position holding each (ascending within a column), and
 // ptr[k] (k in [0, n]) the first entry with a column >= k.  tk, tv: two
 // int32[m] ping-pong buffers each, distinct from the outputs; uses
-// sc.rs_hist, sc.blockcnt and sc.blockoff.
+// sc.rs_hist, sc.blockcnt and sc.blockoff.  rows (optional): one more value
+// per position, carried into rows_out in the same order (tr: its two
+// ping-pong buffers).
 hipError_t launch_radix_transpose(const int32_t* keys, int32_t m, int32_t n, int32_t* keys_out, int32_t* vals_out,
                                   int32_t* ptr, int32_t* const tk[2], int32_t* const tv[2], Scratch& sc,
-                                  hipStream_t s) {
+                                  hipStream_t s, const int32_t* rows, int32_t* rows_out, int32_t* const tr[2]) {
     if (m == 0) {
         k_fill_i32<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(ptr, n + 1, 0);
         return hipGetLastError();
@@ -634,13 +638,22 @@ hipError_t launch_radix_transpose(const int32_t* keys, int32_t m, int32_t n, int
     const int32_t nh = 256 * nblk;
     const int32_t* kin = keys;
     const int32_t* vin = nullptr;
+    const int32_t* rin = rows;
     for (int p = 0; p < passes; ++p) {
         const int shift = 8 * p;
-        int32_t* kout = p == passes - 1 ? keys_out : tk[p & 1];
-        int32_t* vout = p == passes - 1 ? vals_out : tv[p & 1];
+        const bool last = p == passes - 1;
+        int32_t* kout = last ? keys_out : tk[p & 1];
+        int32_t* vout = last ? vals_out : tv[p & 1];
         k_rs_hist<<<nblk, kBlock, 0, s>>>(kin, m, shift, nblk, sc.rs_hist);
         device_scan(FromArray{sc.rs_hist}, nh, nullptr, sc, sc.rs_hist, nullptr, s);
-        k_rs_scatter<<<nblk, kBlock, 0, s>>>(kin, vin, m, shift, nblk, sc.rs_hist, kout, vout);
+        if (rows) {
+            int32_t* rout = last ? rows_out : tr[p & 1];
+            k_rs_scatter<true><<<nblk, kBlock, 0, s>>>(kin, vin, rin, m, shift, nblk, sc.rs_hist, kout, vout, rout);
+            rin = rout;
+        } else {
+            k_rs_scatter<false><<<nblk, kBlock, 0, s>>>(kin, vin, nullptr, m, shift, nblk, sc.rs_hist, kout, vout,
+                                                        nullptr);
+        }
         kin = kout;
         vin = vout;
     }
@@ -648,18 +661,20 @@ hipError_t launch_radix_transpose(const int32_t* keys, int32_t m, int32_t n, int
     return hipGetLastError();
 }
 
-// In-edge lists of buffer b: the transpose of its columns; every entry's row.
+// In-edge lists of buffer b: the transpose of its columns, with every
+// entry's row carried through the sort.
 hipError_t launch_build_csc(const Buf& b, const Csc& c, int32_t n, int32_t m, Scratch& sc, hipStream_t s) {
     if (m == 0) {
         k_fill_i32<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(c.ptr, n + 1, 0);
         k_fill_i32<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(sc.alive_in, n + 1, 0);
         return hipGetLastError();
     }
+    // ping-pong buffers: scratch that the first pass rebuilds (the hit words hold at least 8 m words)
     int32_t* const tk[2] = {sc.xscan, sc.wave_tasks};
     int32_t* const tv[2] = {sc.cxscan, sc.thread_tasks};
-    hipError_t e = launch_radix_transpose(b.col, m, n, c.key, c.edge, c.ptr, tk, tv, sc, s);
+    int32_t* const tr[2] = {sc.ctail, (int32_t*)sc.hitw};
+    hipError_t e = launch_radix_transpose(b.col, m, n, c.key, c.edge, c.ptr, tk, tv, sc, s, b.src, c.src, tr);
     if (e != hipSuccess) return e;
-    k_csc_rows<<<grid_for(m), kBlock, 0, s>>>(b.src, c.edge, m, c.src);
     k_alive_in_init<<<grid_for(n), kBlock, 0, s>>>(c.ptr, n, sc.alive_in);
     return hipGetLastError();
 }

@@ -43,54 +43,70 @@ __global__ __launch_bounds__(kBlock) void k_validate_rowptr(const int32_t* __res
     if (bad) atomicOr(&ctl->err, bad);
 }
 
-// One thread per row: columns strictly ascending, above the diagonal, below n.
-// Also writes each edge's row into src_out.  Skipped when rowptr is invalid,
-// so a malformed rowptr is never walked.
 // Columns of every row strictly ascending, above the diagonal and below n;
-// also writes the row of every edge.  Each thread takes kValSpan consecutive
-// edges, finds the row of the first by binary search over rowptr (already
-// checked monotone) and walks on, so long rows cost no more than short ones.
+// also writes the row of every edge.  One edge per thread, consecutive edges
+// on consecutive lanes: every workgroup takes kValChunks chunks of kBlock
+// edges, two of its lanes find the rows of a chunk's first and last edge by
+// binary search over rowptr (already checked monotone, so a malformed rowptr
+// is never walked), and every lane finds its own row between those two.
 constexpr int kValSpan = 16;
+constexpr int kValChunks = 8;
 
 // tally: also accumulates the input statistic of the light-graph gate into
 // ctl->merge_work: the tail of every edge's row after it, exactly, plus the
-// length of row kappa (the edge's column) sampled on the first edge of every
-// span of kValSpan edges and weighted by the span's edge count.
+// length of row kappa (the edge's column) sampled on every edge whose position
+// is a multiple of kValSpan and weighted by the edge count of that span.
 __global__ __launch_bounds__(kBlock) void k_validate_rows(const int32_t* __restrict__ rowptr,
                                                         const int32_t* __restrict__ col, int32_t n, int32_t m,
                                                         int32_t* __restrict__ src_out, Ctl* ctl, bool tally) {
-    if (ctl->err) return;
-    const int64_t p0 = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * kValSpan;
-    unsigned long long work = 0ull;
-    if (p0 < m) {
-        // row = last i with rowptr[i] <= p0
-        int32_t lo = 0, hi = n;  // rowptr[lo] <= p0 < rowptr[hi]
+    __shared__ int32_t s_r[2];
+    __shared__ unsigned long long s_work[kBlock / 64];
+    if (ctl->err & 15) return;  // rowptr's own checks (bit 16 is this kernel's, set concurrently)
+    // last row i with rowptr[i] <= x, searched in [lo, hi) with rowptr[lo] <= x < rowptr[hi]
+    auto row_of = [&](int32_t x, int32_t lo, int32_t hi) {
         while (hi - lo > 1) {
             const int32_t mid = lo + ((hi - lo) >> 1);
-            if (rowptr[mid] <= p0) lo = mid;
+            if (rowptr[mid] <= x) lo = mid;
             else hi = mid;
         }
-        int32_t row = lo, next = rowptr[row + 1];
-        const int32_t p1 = (int32_t)min(p0 + kValSpan, (int64_t)m);
-        int bad = 0;
-        for (int32_t p = (int32_t)p0; p < p1; ++p) {
-            while (p >= next) next = rowptr[++row + 1];
-            const int32_t prev = p == rowptr[row] ? row : col[p - 1];
-            const int32_t c = col[p];
-            const bool b = (c <= prev) | (c >= n);
-            bad |= b;
-            src_out[p] = row;
-            if (tally && !b) {
-                work += (unsigned long long)(next - p - 1);
-                if (p == p0) work += (unsigned long long)(p1 - p0) * (unsigned long long)(rowptr[c + 1] - rowptr[c]);
-            }
+        return lo;
+    };
+    unsigned long long work = 0ull;
+    int bad = 0;
+    for (int c = 0; c < kValChunks; ++c) {
+        const int64_t q0 = ((int64_t)blockIdx.x * kValChunks + c) * kBlock;
+        if (q0 >= m) break;  // workgroup-uniform
+        const int32_t p0 = (int32_t)q0, plast = (int32_t)min(q0 + kBlock, (int64_t)m) - 1;
+        __syncthreads();  // the previous chunk's readers are done with s_r
+        if (threadIdx.x < 2) s_r[threadIdx.x] = row_of(threadIdx.x == 0 ? p0 : plast, 0, n);
+        __syncthreads();
+        const int32_t p = p0 + (int32_t)threadIdx.x;
+        if (p > plast) continue;
+        const int32_t row = row_of(p, s_r[0], s_r[1] + 1);
+        const int32_t prev = p == rowptr[row] ? row : col[p - 1];
+        const int32_t cv = col[p];
+        const bool b = (cv <= prev) | (cv >= n);
+        bad |= b;
+        src_out[p] = row;
+        if (tally && !b) {
+            work += (unsigned long long)(rowptr[row + 1] - p - 1);
+            if (p % kValSpan == 0)
+                work += (unsigned long long)(min(p + kValSpan, m) - p) *
+                        (unsigned long long)(rowptr[cv + 1] - rowptr[cv]);
         }
-        if (bad) atomicOr(&ctl->err, 16);
     }
+    if (bad) atomicOr(&ctl->err, 16);
     if (tally) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) work += __shfl_xor(work, o);
-        if (__lane_id() == 0 && work) atomicAdd(&ctl->merge_work, work);
+        if (__lane_id() == 0) s_work[threadIdx.x >> 6] = work;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            unsigned long long t = 0ull;
+#pragma unroll
+            for (int i = 0; i < kBlock / 64; ++i) t += s_work[i];
+            if (t) atomicAdd(&ctl->merge_work, t);
+        }
     }
 }
 
@@ -106,7 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_init_eid_s(int32_t* __restrict__ eid
 __global__ __launch_bounds__(kBlock) void k_mark_level(Buf b, const Ctl* __restrict__ ctl, int f, int32_t K,
                                                      int32_t* __restrict__ trussness) {
     const int32_t e = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
-    if (e < ctl->m_buf[f]) trussness[b.eid[e]] = K;
+    if (e < ctl->m_buf[f] && b.S[e] >= 0) trussness[b.eid[e]] = K;  // S < 0: removed in place
 }
 
 __global__ __launch_bounds__(kBlock) void k_fill_value(int32_t* __restrict__ a, int32_t n, int32_t v) {
@@ -134,9 +150,11 @@ __global__ __launch_bounds__(kBlock) void k_scatter_out(Buf b0, Buf b1, const Ct
     const int32_t m_f = ctl->m_buf[f];
     const int32_t e = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
     if (e >= m_f) return;
+    const int32_t v = b.S[e];
+    if (v < 0) return;  // removed by an in-place round (outputs were zeroed)
     const int32_t c = b.eid[e];
     if (mask) mask[c] = 1;
-    support[c] = b.S[e];
+    support[c] = v;
 }
 
 __global__ void k_zero_u64(unsigned long long* p) {
@@ -167,8 +185,8 @@ hipError_t launch_validate(const int32_t* rowptr, const int32_t* col, int32_t n,
     k_ctl_reset<<<1, 64, 0, s>>>(ctl, m);
     k_validate_rowptr<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(rowptr, n, m, ctl);
     if (n > 0 && m > 0)
-        k_validate_rows<<<grid_for(((int64_t)m + kValSpan - 1) / kValSpan), kBlock, 0, s>>>(rowptr, col, n, m, src_out,
-                                                                                           ctl, tally);
+        k_validate_rows<<<(unsigned)(((int64_t)m + (int64_t)kValChunks * kBlock - 1) / ((int64_t)kValChunks * kBlock)),
+                          kBlock, 0, s>>>(rowptr, col, n, m, src_out, ctl, tally);
     return hipGetLastError();
 }
 

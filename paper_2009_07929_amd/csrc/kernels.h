@@ -24,8 +24,9 @@ hipError_t launch_prune_canonical(const int32_t* support, uint8_t* alive, int32_
 // ---- prune + compaction of buffer p into buffer 1-p (k_compact.hip)
 // mode 0: keep = S[e] >= thr (a prune round: updates the pass count and the
 // fixpoint flag); mode 1: keep = alive_can[eid[e]] != 0 (restriction to a
-// caller's alive set).  The in-edge lists are compacted too when cx, cy are
-// given.
+// caller's alive set); mode 2: keep = S[e] >= thr without the round's
+// bookkeeping (the survivors of in-place rounds, before a recomputation).
+// The in-edge lists are compacted too when cx, cy are given.
 // With a batch context (b.thrv set) the threshold is per vertex, edges of
 // graphs finished in this pass are written to the outputs and dropped, and
 // the run ends when no edge is left.  m_hint bounds the alive edges, csc_hint
@@ -43,6 +44,17 @@ hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* 
                           const uint8_t* alive_can, const BatchCtx& b, Scratch& sc, Ctl* ctl, int p, int32_t m_hint,
                           int32_t csc_hint, const PeelSpec& peel, hipStream_t s);
 // The peel itself (k_peel.hip), on buffer x's graph, survivors' supports in y.
+// One in-place prune round of incremental maintenance on buffer x (no
+// compaction): removed edges marked and listed in frontier, bookkeeping in
+// ctl, then their triangles peeled unless ratio > 0 and the frontier exceeds
+// ratio x the survivors (ctl->need_support).
+hipError_t launch_state_round(const Buf& x, const Csc& c, int32_t thr, int32_t* frontier, Scratch& sc, Ctl* ctl,
+                              int p, float ratio, int32_t m_hint, hipStream_t s);
+// Its marking (k_compact.hip): alive edges of x with S < thr become kDying
+// and are listed in frontier (Ctl::front_n of them), the previous round's
+// kDying edges become kDead.
+hipError_t launch_state_mark(const Buf& x, int32_t thr, int32_t* frontier, Scratch& sc, Ctl* ctl, int p,
+                             int32_t m_hint, hipStream_t s);
 hipError_t launch_peel(const Buf& x, const Buf& y, const Csc& c, const KeepWord* keepw, const int32_t* frontier,
                        Ctl* ctl, int p, float ratio, int32_t m_hint, hipStream_t s);
 // Zeroes the supports of buffer p's alive edges (a recomputation follows a
@@ -62,7 +74,8 @@ hipError_t launch_batch_status(const Buf& x, const BatchCtx& b, int32_t G, const
 // tk, tv: int32[m] ping-pong buffers distinct from the outputs.
 hipError_t launch_radix_transpose(const int32_t* keys, int32_t m, int32_t n, int32_t* keys_out, int32_t* vals_out,
                                   int32_t* ptr, int32_t* const tk[2], int32_t* const tv[2], Scratch& sc,
-                                  hipStream_t s);
+                                  hipStream_t s, const int32_t* rows = nullptr, int32_t* rows_out = nullptr,
+                                  int32_t* const tr[2] = nullptr);
 // out[j] = the row of CSR position pos[j].
 hipError_t launch_rows_of(const int32_t* rowptr, int32_t nrows, const int32_t* pos, int32_t m, int32_t* out,
                           hipStream_t s);
