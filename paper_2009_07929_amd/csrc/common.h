@@ -17,7 +17,7 @@ constexpr int kScanThreads = 1024;
 constexpr int kHubThreads = 256;     // 4 waves
 constexpr int kHubChunk = 256;       // tasks (in-edges of one row kappa) per hub item
 constexpr int kHubUnroll = 8;        // tail chunks whose loads a hub wave issues together
-constexpr int kHubBatch = 4;         // consecutive hub items per ticket of the persistent hub kernel
+constexpr int kHubBatch = 8;         // consecutive hub items per ticket of the persistent hub kernel
 // LDS of one hub workgroup: the rank bitmap (or the keys) and the accumulators
 // of row kappa, about 24.6 KB, so that the six workgroups per CU that the
 // kernel's register use allows all fit in the 160 KB of a CU.

@@ -186,19 +186,23 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
         const unsigned long long far = __ballot(dfar);
         const int32_t nch = min(64, C - b0);
         uint32_t word_lo = 0, word_hi = 0;
-        for (int32_t jj = 0; jj < nch; jj += kHubUnroll) {
-            int32_t ub[kHubUnroll], ul[kHubUnroll], uw[kHubUnroll];
+        // step j0: the descriptors of chunks j0 .. j0 + kHubUnroll - 1 (readlane;
+        // j0 + u <= 63, lanes at or past nch carry dbase = dlen = 0) and their
+        // tail loads, unconditional at the chunk's base plus the lane: lanes past
+        // a chunk read up to 63 elements further (the column arrays carry that
+        // much slack) and are masked when processed
+        auto load_step = [&](int32_t j0, int32_t(&ub)[kHubUnroll], int32_t(&ul)[kHubUnroll],
+                             int32_t(&uw)[kHubUnroll]) {
 #pragma unroll
             for (int u = 0; u < kHubUnroll; ++u) {
-                // jj + u <= 63; lanes at or past nch carry dbase = dlen = 0
-                ub[u] = __builtin_amdgcn_readlane(dbase, jj + u);
-                ul[u] = __builtin_amdgcn_readlane(dlen, jj + u);
+                ub[u] = __builtin_amdgcn_readlane(dbase, j0 + u);
+                ul[u] = __builtin_amdgcn_readlane(dlen, j0 + u);
             }
-            // unconditional loads at a scalar base and the lane offset: lanes
-            // past a chunk read up to 63 elements further (the column arrays
-            // carry that much slack) and are masked below
 #pragma unroll
             for (int u = 0; u < kHubUnroll; ++u) uw[u] = (col + (uint32_t)ub[u])[(uint32_t)lane];  // ub >= 0
+        };
+        auto process_step = [&](int32_t j0, const int32_t(&ub)[kHubUnroll], const int32_t(&ul)[kHubUnroll],
+                                const int32_t(&uw)[kHubUnroll]) {
             unsigned long long hb[kHubUnroll];
             if (MODE == kModeBitmap) {
                 // all chunks' bitmap words first (independent LDS reads), then
@@ -218,8 +222,11 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
                     const bool in = (uint32_t)lane < (uint32_t)ul[u];
                     hb[u] = __builtin_amdgcn_uicmp(bit, 0u, 33 /* ne */) &
                             __builtin_amdgcn_uicmp((uint32_t)lane, (uint32_t)ul[u], 36 /* ult */);
+                    // the word's high half is the byte offset in s_acc of its first set bit's
+                    // entry; ubfe takes its width modulo 32, so the bits below off are counted
                     if (bit && in)
-                        atomicAdd(&s_acc[(uint32_t)(bw[u] >> 32) + __popc(__builtin_amdgcn_ubfe(bits, 0u, off[u] & 31u))],
+                        atomicAdd(reinterpret_cast<int32_t*>(reinterpret_cast<char*>(s_acc) + (uint32_t)(bw[u] >> 32) +
+                                                             (__popc(__builtin_amdgcn_ubfe(bits, 0u, off[u])) << 2)),
                                   1);
                 }
             } else {
@@ -248,7 +255,7 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
             // the chunk's hit word goes to its lane
 #pragma unroll
             for (int u = 0; u < kHubUnroll; ++u) {
-                if (lane == jj + u) {
+                if (lane == j0 + u) {
                     word_lo = (uint32_t)hb[u];
                     word_hi = (uint32_t)(hb[u] >> 32);
                 }
@@ -257,9 +264,14 @@ __device__ __forceinline__ void hub_tasks(const Buf& x, unsigned long long* __re
             if (far) {
 #pragma unroll
                 for (int u = 0; u < kHubUnroll; ++u)
-                    if (jj + u < nch && ((far >> (jj + u)) & 1ull) && ((hb[u] >> lane) & 1ull))
+                    if (j0 + u < nch && ((far >> (j0 + u)) & 1ull) && ((hb[u] >> lane) & 1ull))
                         atomicAdd(&x.S[ub[u] + lane], 1);
             }
+        };
+        for (int32_t jj = 0; jj < nch; jj += kHubUnroll) {
+            int32_t ub[kHubUnroll], ul[kHubUnroll], uw[kHubUnroll];
+            load_step(jj, ub, ul, uw);
+            process_step(jj, ub, ul, uw);
         }
         // block end: lane j writes chunk j's hit word and adds its hits to S(i, kappa)
         const unsigned long long word = ((unsigned long long)word_hi << 32) | word_lo;
@@ -285,7 +297,7 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
                                                            unsigned long long* __restrict__ hitw,
                                                            const int64_t* __restrict__ hwoff, int64_t hit_cap,
                                                            unsigned long long* __restrict__ cycles) {
-    __shared__ uint2 s_bm[kSpanWords + 1];  // rank bitmap {bits, set bits before this word} + a zero guard word; or keys
+    __shared__ uint2 s_bm[kSpanWords + 1];  // rank bitmap {bits, 4 x set bits before this word} + a zero guard word; or keys
     __shared__ int32_t s_acc[kKeyCap];
     __shared__ int s_wave[kHubThreads / 64];
     __shared__ int32_t s_it;
@@ -351,8 +363,8 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
                     for (int32_t j = j0; j < j1; ++j) local += __popc(s_bm[j].x);
                     int tot;
                     int run = block_excl_sum<kHubThreads>(local, s_wave, tot);
-                    for (int32_t j = j0; j < j1; ++j) {
-                        s_bm[j].y = (uint32_t)run;
+                    for (int32_t j = j0; j < j1; ++j) {  // byte offset of the word's first entry in s_acc
+                        s_bm[j].y = (uint32_t)run * 4u;
                         run += __popc(s_bm[j].x);
                     }
                 } else if (cur_mode == kModeKeys) {
