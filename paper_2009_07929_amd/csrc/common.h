@@ -126,6 +126,14 @@ struct alignas(16) KeepWord {
     int32_t pad;
 };
 
+// Liveness of an in-place round, 64 positions to a word: removed by an
+// earlier round (dead) or by this one (dying).  Same size as a KeepWord, and
+// kept in the same scratch (the two are never live at once).
+struct alignas(16) LiveWord {
+    unsigned long long dead;
+    unsigned long long dying;
+};
+
 // Per-run scratch arrays inside the workspace.
 struct Scratch {
     int32_t* xscan;       // int32[m+1]: new CSR position of every old position

@@ -358,7 +358,8 @@ __global__ __launch_bounds__(kScanThreads) void k_state_scan(const int32_t* __re
 
 __global__ __launch_bounds__(kBlock) void k_state_scatter(Buf x, const Ctl* __restrict__ ctl, int p, int32_t thr,
                                                         const int32_t* __restrict__ blockoff,
-                                                        int32_t* __restrict__ frontier) {
+                                                        int32_t* __restrict__ frontier,
+                                                        LiveWord* __restrict__ livew) {
     __shared__ int s_wave[kBlock / 64];
     if (ctl->done) return;
     int32_t lo, hi;
@@ -376,6 +377,10 @@ __global__ __launch_bounds__(kBlock) void k_state_scatter(Buf x, const Ctl* __re
         } else if (d == kDying) {
             x.S[i] = kDead;
         }
+        // the round's liveness words (i is the first of its wave's 64 positions on lane 0)
+        const unsigned long long dead = __ballot(i < hi && (d == kDead || d == kDying));
+        const unsigned long long dying = __ballot(k);
+        if (__lane_id() == 0 && i < hi) livew[i >> 6] = LiveWord{dead, dying};
         base += tot;
     }
 }
@@ -411,7 +416,8 @@ hipError_t launch_state_mark(const Buf& x, int32_t thr, int32_t* frontier, Scrat
     const int32_t G = filter_grid(m_hint);
     k_state_count<<<G, kBlock, 0, s>>>(x, ctl, p, thr, sc.blockcnt);
     k_state_scan<<<1, kScanThreads, 0, s>>>(sc.blockcnt, sc.blockoff, G, ctl);
-    k_state_scatter<<<G, kBlock, 0, s>>>(x, ctl, p, thr, sc.blockoff, frontier);
+    k_state_scatter<<<G, kBlock, 0, s>>>(x, ctl, p, thr, sc.blockoff, frontier,
+                                         reinterpret_cast<LiveWord*>(sc.keepw));
     return hipGetLastError();
 }
 

@@ -149,7 +149,10 @@ __global__ void k_state_decide(Ctl* ctl, int p, float ratio) {
     if (ratio > 0.f && (double)nf > (double)ratio * (double)ctl->kept) ctl->need_support = 1;
 }
 
+// The liveness of an edge comes from the round's LiveWords (a table 1/16 the
+// size of S, written by the marking), not from S itself.
 __global__ __launch_bounds__(kBlock) void k_peel_state(Buf x, Csc c, const int32_t* __restrict__ frontier,
+                                                     const LiveWord* __restrict__ livew,
                                                      const Ctl* __restrict__ ctl) {
     if (ctl->done || ctl->need_support) return;
     const int32_t nf = ctl->front_n;
@@ -157,15 +160,15 @@ __global__ __launch_bounds__(kBlock) void k_peel_state(Buf x, Csc c, const int32
     const int32_t nw = (int32_t)(gridDim.x * (kBlock / 64));
     for (int32_t wid = (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 6); wid < nf; wid += nw) {
         const int32_t f = frontier[wid];
-        // a survivor's S stays >= 0 throughout (it loses at most the triangles
-        // it closes), so kDying and kDead read the same while others decrement
         auto charge = [&](int32_t e1, int32_t e2) {
             if (e1 < 0 || e2 < 0) return;  // tombstones of the in-lists: removed before the last compaction
-            const int32_t s1 = S[e1], s2 = S[e2];
-            if (s1 == kDead || s2 == kDead) return;  // not a triangle of this round
-            if ((s1 == kDying && e1 < f) || (s2 == kDying && e2 < f)) return;
-            if (s1 != kDying) atomicSub(&S[e1], 1);
-            if (s2 != kDying) atomicSub(&S[e2], 1);
+            const LiveWord w1 = livew[e1 >> 6], w2 = livew[e2 >> 6];
+            const int b1 = e1 & 63, b2 = e2 & 63;
+            if (((w1.dead >> b1) | (w2.dead >> b2)) & 1ull) return;  // not a triangle of this round
+            const bool y1 = (w1.dying >> b1) & 1ull, y2 = (w2.dying >> b2) & 1ull;
+            if ((y1 && e1 < f) || (y2 && e2 < f)) return;
+            if (!y1) atomicSub(&S[e1], 1);
+            if (!y2) atomicSub(&S[e2], 1);
         };
         peel_triangles(x, c, f, charge);
     }
@@ -191,7 +194,7 @@ hipError_t launch_state_round(const Buf& x, const Csc& c, int32_t thr, int32_t* 
     k_state_decide<<<1, 64, 0, s>>>(ctl, p, ratio);
     if (m_hint > 0) {
         const unsigned grid = min(grid_for((int64_t)m_hint * 64), (unsigned)kStreamMaxGrid);
-        k_peel_state<<<grid, kBlock, 0, s>>>(x, c, frontier, ctl);
+        k_peel_state<<<grid, kBlock, 0, s>>>(x, c, frontier, reinterpret_cast<const LiveWord*>(sc.keepw), ctl);
     }
     return hipGetLastError();
 }
