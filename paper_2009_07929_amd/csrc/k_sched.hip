@@ -231,9 +231,11 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const int32_t* __restrict
                                                      int32_t* __restrict__ rows_out) {
     constexpr int kWaves = kBlock / 64;
     constexpr int kPerWave = kRsTile / kWaves;
-    __shared__ int32_t s_k[kRsTile];
-    __shared__ int32_t s_v[kRsTile];
-    __shared__ int32_t s_w[kRow ? kRsTile : 1];
+    // one staging array, reused for keys, values and rows in turn, and the
+    // digit of every sorted slot: a small LDS footprint keeps several
+    // workgroups per CU, whose loads overlap each other's ranking
+    __shared__ int32_t s_x[kRsTile];
+    __shared__ uint8_t s_d[kRsTile];
     __shared__ int s_cnt[kWaves][256];  // per-wave digit counts, then each wave's offset within its digit
     __shared__ int s_loc[256];          // first tile-local slot of every digit
     __shared__ int s_glob[256];         // first output position of every digit's run of this tile
@@ -242,21 +244,25 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const int32_t* __restrict
 #pragma unroll
     for (int i = 0; i < kWaves; ++i) s_cnt[i][t] = 0;
     s_glob[t] = off[(int64_t)t * nblk + blockIdx.x];
-    __syncthreads();
     const int32_t tile0 = (int32_t)blockIdx.x * kRsTile;
     const int32_t base = tile0 + w * kPerWave;
     const uint64_t lt = (1ull << lane) - 1ull;
     int32_t kreg[kRsItems], vreg[kRsItems], rreg[kRow ? kRsItems : 1];
     int rank[kRsItems];
+    // every load of the wave's quarter first, then the ranking
 #pragma unroll
     for (int j = 0; j < kRsItems; ++j) {
         const int32_t e = base + j * 64 + lane;
         const bool valid = e < N;
-        const int32_t key = valid ? keys[e] : 0;
-        kreg[j] = key;
+        kreg[j] = valid ? keys[e] : 0;
         vreg[j] = valid ? (vals ? vals[e] : e) : 0;
         if constexpr (kRow) rreg[j] = valid ? rows[e] : 0;
-        const int d = (key >> shift) & 255;
+    }
+    __syncthreads();  // counters cleared
+#pragma unroll
+    for (int j = 0; j < kRsItems; ++j) {
+        const bool valid = base + j * 64 + lane < N;
+        const int d = (kreg[j] >> shift) & 255;
         uint64_t match = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -291,25 +297,30 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const int32_t* __restrict
     for (int i = 0; i < w; ++i) wpre += s_ws[i];
     s_loc[t] = wpre + incl - tot;
     __syncthreads();
+    // sorted slot of every pair
 #pragma unroll
     for (int j = 0; j < kRsItems; ++j) {
         if (rank[j] < 0) continue;
         const int d = (kreg[j] >> shift) & 255;
-        const int l = s_loc[d] + s_cnt[w][d] + rank[j];
-        s_k[l] = kreg[j];
-        s_v[l] = vreg[j];
-        if constexpr (kRow) s_w[l] = rreg[j];
+        rank[j] += s_loc[d] + s_cnt[w][d];
+        s_d[rank[j]] = (uint8_t)d;
     }
-    __syncthreads();
     const int32_t nvalid = min((int32_t)kRsTile, N - tile0);
-    for (int i = t; i < nvalid; i += kBlock) {
-        const int32_t key = s_k[i];
-        const int d = (key >> shift) & 255;
-        const int32_t pos = s_glob[d] + (i - s_loc[d]);
-        keys_out[pos] = key;
-        vals_out[pos] = s_v[i];
-        if constexpr (kRow) rows_out[pos] = s_w[i];
-    }
+    // one array at a time: stage in sorted order, then write each digit's run
+    auto pass = [&](const int32_t* reg, int32_t* __restrict__ out) {
+#pragma unroll
+        for (int j = 0; j < kRsItems; ++j)
+            if (rank[j] >= 0) s_x[rank[j]] = reg[j];
+        __syncthreads();
+        for (int i = t; i < nvalid; i += kBlock) {
+            const int d = s_d[i];
+            out[s_glob[d] + (i - s_loc[d])] = s_x[i];
+        }
+        __syncthreads();  // s_x is read before the next array overwrites it
+    };
+    pass(kreg, keys_out);
+    pass(vreg, vals_out);
+    if constexpr (kRow) pass(rreg, rows_out);
 }
 
 // cptr[k] = first position of the sorted keys holding a value >= k, k in [0, n]
