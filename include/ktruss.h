@@ -75,14 +75,15 @@ typedef struct ktruss_tuning {
                                 kappa; the row-kappa lengths sampled on edges 0, 16, 32, ... and weighted
                                 by 16) is at most this, ktruss_run/ktruss_support use thread-per-edge for
                                 every task and build no in-edge lists; 0: default 32, negative: never */
-    int32_t incremental;     /* ktruss_run / ktruss_decompose / ktruss_run_batched: 0 recompute every pass's supports (Algorithm 1);
-                                1 after the first pass, keep the survivors' supports and take off each triangle a
-                                prune destroys (incremental maintenance); 2 as 1, except that a prune removing
-                                more than peel_ratio x the edges it keeps is followed by a recomputation.  Masks,
-                                supports and pass counts are the same in every mode.  Rounds replayed from a
-                                hipGraph (rounds_per_sync >= 2) use mode 1 for 2.  Also for ktruss_run_batched
-                                (the edges of a graph that finishes leave the working set without destroying
-                                triangles). */
+    int32_t incremental;     /* ktruss_run / ktruss_decompose / ktruss_run_batched: 0 recompute every pass's
+                                supports (Algorithm 1); 1 after the first pass, keep the survivors' supports and
+                                take off each triangle a prune destroys (incremental maintenance; the prunes
+                                mark edges in place, nothing is compacted); 2 as 1, except that a prune removing
+                                more than peel_ratio x the edges it keeps is followed by a compaction and a
+                                recomputation.  Masks, supports and pass counts are the same in every mode.
+                                Rounds replayed from a hipGraph (rounds_per_sync >= 2) use mode 1 for 2.  In
+                                ktruss_run_batched a graph that finishes keeps its edges in place; they destroy
+                                no triangle. */
     float peel_ratio;        /* incremental = 2: the ratio above (0: the default 0.125) */
 } ktruss_tuning;
 

@@ -41,7 +41,7 @@ namespace {
 // batched form, G graphs.
 struct FullLayout {
     Layout L;
-    size_t gidv, thrv, graph_done, done_now;
+    size_t gidv, thrv, graph_done, done_now, low_cnt;
 };
 
 FullLayout full_layout(int32_t n, int64_t m, int32_t G) {
@@ -98,6 +98,7 @@ FullLayout full_layout(int32_t n, int64_t m, int32_t G) {
         F.thrv = take(vn);
         F.graph_done = take((size_t)G);
         F.done_now = take((size_t)G);
+        F.low_cnt = take(sizeof(int32_t) * (size_t)G);
     }
     L.total = off;
     return F;
@@ -159,6 +160,7 @@ Work carve(void* work, int32_t n, int64_t m, int32_t G) {
         w.batch.thrv = (int32_t*)(base + F.thrv);
         w.batch.graph_done = (uint8_t*)(base + F.graph_done);
         w.batch.done_now = (uint8_t*)(base + F.done_now);
+        w.batch.low_cnt = (int32_t*)(base + F.low_cnt);
     }
     return w;
 }
@@ -545,8 +547,8 @@ hipStream_t capture_stream(hipError_t& e) {
     return cs;
 }
 
-// In-place rounds: incremental maintenance of one graph (not sampling costs).
-bool in_place(const RunSpec& r) { return r.incremental != 0 && r.G == 0 && !r.collect; }
+// In-place rounds: incremental maintenance (not while sampling costs).
+bool in_place(const RunSpec& r) { return r.incremental != 0 && !r.collect; }
 
 // In-place rounds replayed from a hipGraph, two per replay, ceil(rps / 2)
 // replays between host checks; every round peels (mode 1), so the buffer
@@ -559,8 +561,9 @@ int32_t state_rounds_graph(const RunSpec& r, Work& w, int p, int32_t m_hint, Ctl
     hipGraphExec_t exec = nullptr;
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
     t_capturing = true;
-    e = launch_state_round(w.b[p], w.c[p], r.thr, w.sc.thread_tasks, w.sc, w.ctl, p, 0.f, m_hint, cs);
-    if (e == hipSuccess) e = launch_state_round(w.b[p], w.c[p], r.thr, w.sc.thread_tasks, w.sc, w.ctl, p, 0.f, m_hint, cs);
+    for (int i = 0; i < 2 && e == hipSuccess; ++i)
+        e = launch_state_round(w.b[p], w.c[p], r.thr, w.batch, r.G, w.sc.thread_tasks, w.sc, w.ctl, p, 0.f, m_hint,
+                               cs);
     t_capturing = false;
     hipError_t ec = hipStreamEndCapture(cs, &graph);
     if (e != hipSuccess) {
@@ -599,7 +602,8 @@ int32_t state_rounds(const RunSpec& r, Work& w, int p, int32_t m_hint, Ctl& h, h
     if (r.tuning.rounds_per_sync >= 2) return state_rounds_graph(r, w, p, m_hint, h, s);
     const float ratio = peel_of(r).ratio;
     for (;;) {
-        HIP_TRY(launch_state_round(w.b[p], w.c[p], r.thr, w.sc.thread_tasks, w.sc, w.ctl, p, ratio, m_hint, s),
+        HIP_TRY(launch_state_round(w.b[p], w.c[p], r.thr, w.batch, r.G, w.sc.thread_tasks, w.sc, w.ctl, p, ratio,
+                                   m_hint, s),
                 "in-place round");
         int32_t rc = read_ctl(w, h, s);
         if (rc != KTRUSS_OK || h.done) return rc;
@@ -1018,6 +1022,7 @@ int32_t ktruss_run_batched(const ktruss_batch* b, const int32_t* K, uint8_t* mas
     w.batch.vert_off = b->vert_off;
     w.batch.mask = mask;
     w.batch.support = support;
+    w.batch.rounds = rounds;
     rc = validate_on_device(b->rowptr, b->col, n, m, w, w.b[0].src, s);
     if (rc != KTRUSS_OK) return rc;
     HIP_TRY(launch_batch_setup(w.batch, G, n, K, w.b[0].src, b->col, m, w.ctl, s), "batch set-up");
@@ -1048,6 +1053,9 @@ int32_t ktruss_run_batched(const ktruss_batch* b, const int32_t* K, uint8_t* mas
     Ctl h{};
     rc = run_rounds(r, w, s, h);
     if (rc != KTRUSS_OK) return rc;
+    // in-place rounds leave every graph's truss in the final buffer (the
+    // compacting rounds wrote each graph out when it finished)
+    if (in_place(r)) HIP_TRY(launch_scatter_out(w.b[0], w.b[1], w.ctl, mask, support, m, s), "scatter");
     HIP_TRY(hipStreamSynchronize(s), "batch sync");
     return KTRUSS_OK;
 }

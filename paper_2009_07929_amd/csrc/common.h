@@ -174,6 +174,8 @@ struct BatchCtx {
     uint8_t* done_now;        // uint8[G]: finished in the current pass
     uint8_t* mask;            // outputs, canonical positions of the union
     int32_t* support;
+    int32_t* low_cnt;         // int32[G]: edges an in-place round removes, per graph (zero between rounds)
+    int32_t* rounds;          // int32[G]: the caller's per-graph pass counts
 };
 
 // Hit words of the hub kernel.  A task whose tail has L elements owns

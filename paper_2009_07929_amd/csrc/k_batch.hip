@@ -58,12 +58,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_edges(const int32_t* __restric
 }
 
 __global__ __launch_bounds__(kBlock) void k_batch_reset(int32_t G, int32_t* __restrict__ rounds,
-                                                      uint8_t* __restrict__ graph_done, uint8_t* __restrict__ done_now) {
+                                                      uint8_t* __restrict__ graph_done, uint8_t* __restrict__ done_now,
+                                                      int32_t* __restrict__ low_cnt) {
     const int32_t g = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
     if (g >= G) return;
     rounds[g] = 0;
     graph_done[g] = 0;
     done_now[g] = 0;
+    low_cnt[g] = 0;
 }
 
 // After a support pass over buffer p: for every unfinished graph, count the
@@ -106,7 +108,7 @@ hipError_t launch_batch_setup(const BatchCtx& b, int32_t G, int32_t n_total, con
 }
 
 hipError_t launch_batch_reset(const BatchCtx& b, int32_t G, int32_t* rounds, hipStream_t s) {
-    if (G > 0) k_batch_reset<<<grid_for(G), kBlock, 0, s>>>(G, rounds, b.graph_done, b.done_now);
+    if (G > 0) k_batch_reset<<<grid_for(G), kBlock, 0, s>>>(G, rounds, b.graph_done, b.done_now, b.low_cnt);
     return hipGetLastError();
 }
 

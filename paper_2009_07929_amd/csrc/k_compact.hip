@@ -334,16 +334,20 @@ __global__ void k_csc_pack_end(Ctl* ctl) {
 // ---- marking of an in-place round: the same count / scan / scatter as the
 // filter, writing only the removed edges' positions (in position order) and
 // their marks.
+// The threshold of edge e: the run's, or its graph's in the batched form.
+__device__ __forceinline__ int32_t state_thr(const Buf& x, const BatchCtx& b, int32_t thr, int32_t e) {
+    return b.thrv ? b.thrv[x.src[e]] : thr;
+}
 __device__ __forceinline__ bool state_dying(int32_t d, int32_t thr) { return d >= 0 && d < thr; }
 
-__global__ __launch_bounds__(kBlock) void k_state_count(Buf x, const Ctl* __restrict__ ctl, int p, int32_t thr,
-                                                      int32_t* __restrict__ blockcnt) {
+__global__ __launch_bounds__(kBlock) void k_state_count(Buf x, BatchCtx b, const Ctl* __restrict__ ctl, int p,
+                                                      int32_t thr, int32_t* __restrict__ blockcnt) {
     __shared__ int s_wave[kBlock / 64];
     if (ctl->done) return;
     int32_t lo, hi;
     chunk_of(ctl->m_buf[p], lo, hi);
     int c = 0;
-    for (int32_t i = lo + (int32_t)threadIdx.x; i < hi; i += kBlock) c += state_dying(x.S[i], thr);
+    for (int32_t i = lo + (int32_t)threadIdx.x; i < hi; i += kBlock) c += state_dying(x.S[i], state_thr(x, b, thr, i));
     c = block_sum<kBlock>(c, s_wave);
     if (threadIdx.x == 0) blockcnt[blockIdx.x] = c;
 }
@@ -356,8 +360,8 @@ __global__ __launch_bounds__(kScanThreads) void k_state_scan(const int32_t* __re
     if (threadIdx.x == 0) ctl->front_n = total;
 }
 
-__global__ __launch_bounds__(kBlock) void k_state_scatter(Buf x, const Ctl* __restrict__ ctl, int p, int32_t thr,
-                                                        const int32_t* __restrict__ blockoff,
+__global__ __launch_bounds__(kBlock) void k_state_scatter(Buf x, BatchCtx b, const Ctl* __restrict__ ctl, int p,
+                                                        int32_t thr, const int32_t* __restrict__ blockoff,
                                                         int32_t* __restrict__ frontier,
                                                         LiveWord* __restrict__ livew) {
     __shared__ int s_wave[kBlock / 64];
@@ -365,10 +369,26 @@ __global__ __launch_bounds__(kBlock) void k_state_scatter(Buf x, const Ctl* __re
     int32_t lo, hi;
     chunk_of(ctl->m_buf[p], lo, hi);
     int32_t base = blockoff[blockIdx.x];
+    const int lane = __lane_id();
     for (int32_t t0 = lo; t0 < hi; t0 += kBlock) {
         const int32_t i = t0 + (int32_t)threadIdx.x;
         const int32_t d = i < hi ? x.S[i] : kDead;
-        const bool k = state_dying(d, thr);
+        const bool k = i < hi && state_dying(d, state_thr(x, b, thr, i));
+        if (b.thrv) {
+            // per-graph counts of the removed edges: a graph's edges are
+            // consecutive, so a segmented sum over the wave gives one atomic
+            // per graph piece
+            const int32_t key = i < hi ? b.gidv[x.src[i]] : -1;
+            int32_t v = k ? 1 : 0;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t u = __shfl_up(v, o);
+                const int32_t kk = __shfl_up(key, o);
+                if (lane >= o && kk == key) v += u;
+            }
+            const int32_t next = __shfl_down(key, 1);
+            if (i < hi && v && (lane == 63 || next != key)) atomicAdd(&b.low_cnt[key], v);
+        }
         int tot;
         const int32_t q = base + block_excl_flag<kBlock>(k, s_wave, tot);
         if (k) {
@@ -409,15 +429,31 @@ void run_filter(const P& pol, Ctl* ctl, int p, int update, int round, int32_t* b
     k_filter_scatter<P><<<G, kBlock, 0, s>>>(pol, ctl, p, round, blockoff, xscan, keepw);
 }
 
+// Batched form, after the marking: every unfinished graph counts the pass,
+// and finishes if the round removes none of its edges (its edges then stay
+// put: nothing in the graph changes any more).  Runs before the round's
+// fixpoint check, so the last round counts too.
+__global__ __launch_bounds__(kBlock) void k_state_graphs(BatchCtx b, int32_t G, const Ctl* __restrict__ ctl) {
+    if (ctl->done) return;
+    const int32_t g = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (g >= G) return;
+    if (!b.graph_done[g]) {
+        b.rounds[g] += 1;
+        if (b.low_cnt[g] == 0) b.graph_done[g] = 1;
+    }
+    b.low_cnt[g] = 0;
+}
+
 }  // namespace
 
-hipError_t launch_state_mark(const Buf& x, int32_t thr, int32_t* frontier, Scratch& sc, Ctl* ctl, int p,
-                             int32_t m_hint, hipStream_t s) {
-    const int32_t G = filter_grid(m_hint);
-    k_state_count<<<G, kBlock, 0, s>>>(x, ctl, p, thr, sc.blockcnt);
-    k_state_scan<<<1, kScanThreads, 0, s>>>(sc.blockcnt, sc.blockoff, G, ctl);
-    k_state_scatter<<<G, kBlock, 0, s>>>(x, ctl, p, thr, sc.blockoff, frontier,
-                                         reinterpret_cast<LiveWord*>(sc.keepw));
+hipError_t launch_state_mark(const Buf& x, const BatchCtx& b, int32_t G, int32_t thr, int32_t* frontier, Scratch& sc,
+                             Ctl* ctl, int p, int32_t m_hint, hipStream_t s) {
+    const int32_t grid = filter_grid(m_hint);
+    k_state_count<<<grid, kBlock, 0, s>>>(x, b, ctl, p, thr, sc.blockcnt);
+    k_state_scan<<<1, kScanThreads, 0, s>>>(sc.blockcnt, sc.blockoff, grid, ctl);
+    k_state_scatter<<<grid, kBlock, 0, s>>>(x, b, ctl, p, thr, sc.blockoff, frontier,
+                                            reinterpret_cast<LiveWord*>(sc.keepw));
+    if (b.thrv && G > 0) k_state_graphs<<<grid_for(G), kBlock, 0, s>>>(b, G, ctl);
     return hipGetLastError();
 }
 

@@ -186,10 +186,11 @@ __global__ void k_need_support_clear(Ctl* ctl) {
 
 }  // namespace
 
-hipError_t launch_state_round(const Buf& x, const Csc& c, int32_t thr, int32_t* frontier, Scratch& sc, Ctl* ctl,
-                              int p, float ratio, int32_t m_hint, hipStream_t s) {
+hipError_t launch_state_round(const Buf& x, const Csc& c, int32_t thr, const BatchCtx& b, int32_t G,
+                              int32_t* frontier, Scratch& sc, Ctl* ctl, int p, float ratio, int32_t m_hint,
+                              hipStream_t s) {
     // an empty buffer still takes the round's bookkeeping (it ends the run)
-    const hipError_t e = launch_state_mark(x, thr, frontier, sc, ctl, p, m_hint, s);
+    const hipError_t e = launch_state_mark(x, b, G, thr, frontier, sc, ctl, p, m_hint, s);
     if (e != hipSuccess) return e;
     k_state_decide<<<1, 64, 0, s>>>(ctl, p, ratio);
     if (m_hint > 0) {

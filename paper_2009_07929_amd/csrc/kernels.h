@@ -48,13 +48,16 @@ hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* 
 // compaction): removed edges marked and listed in frontier, bookkeeping in
 // ctl, then their triangles peeled unless ratio > 0 and the frontier exceeds
 // ratio x the survivors (ctl->need_support).
-hipError_t launch_state_round(const Buf& x, const Csc& c, int32_t thr, int32_t* frontier, Scratch& sc, Ctl* ctl,
-                              int p, float ratio, int32_t m_hint, hipStream_t s);
+// With a batch context (b.thrv set) the threshold is per graph and every
+// unfinished graph counts the pass, finishing when none of its edges goes.
+hipError_t launch_state_round(const Buf& x, const Csc& c, int32_t thr, const BatchCtx& b, int32_t G,
+                              int32_t* frontier, Scratch& sc, Ctl* ctl, int p, float ratio, int32_t m_hint,
+                              hipStream_t s);
 // Its marking (k_compact.hip): alive edges of x with S < thr become kDying
 // and are listed in frontier (Ctl::front_n of them), the previous round's
-// kDying edges become kDead.
-hipError_t launch_state_mark(const Buf& x, int32_t thr, int32_t* frontier, Scratch& sc, Ctl* ctl, int p,
-                             int32_t m_hint, hipStream_t s);
+// kDying edges become kDead; the batched form's per-graph pass counts.
+hipError_t launch_state_mark(const Buf& x, const BatchCtx& b, int32_t G, int32_t thr, int32_t* frontier, Scratch& sc,
+                             Ctl* ctl, int p, int32_t m_hint, hipStream_t s);
 hipError_t launch_peel(const Buf& x, const Buf& y, const Csc& c, const KeepWord* keepw, const int32_t* frontier,
                        Ctl* ctl, int p, float ratio, int32_t m_hint, hipStream_t s);
 // Zeroes the supports of buffer p's alive edges (a recomputation follows a
