@@ -44,13 +44,16 @@ __global__ __launch_bounds__(kBlock) void k_validate_rowptr(const int32_t* __res
 }
 
 // Columns of every row strictly ascending, above the diagonal and below n;
-// also writes the row of every edge.  One edge per thread, consecutive edges
-// on consecutive lanes: every workgroup takes kValChunks chunks of kBlock
-// edges, two of its lanes find the rows of a chunk's first and last edge by
-// binary search over rowptr (already checked monotone, so a malformed rowptr
-// is never walked), and every lane finds its own row between those two.
+// also writes the row of every edge.  Every workgroup takes a tile of
+// kValTile consecutive edges: two of its lanes find the rows of the tile's
+// first and last edge by binary search over rowptr (already checked
+// monotone, so a malformed rowptr is never walked), every row in between
+// marks the tile slot where it starts (the largest row wins, so empty rows
+// give way), and a max-scan over the tile gives every edge its row.  The
+// lanes then check their 8 consecutive edges.
 constexpr int kValSpan = 16;
-constexpr int kValChunks = 8;
+constexpr int kValPer = 8;
+constexpr int kValTile = kBlock * kValPer;
 
 // tally: also accumulates the input statistic of the light-graph gate into
 // ctl->merge_work: the tail of every edge's row after it, exactly, plus the
@@ -59,53 +62,90 @@ constexpr int kValChunks = 8;
 __global__ __launch_bounds__(kBlock) void k_validate_rows(const int32_t* __restrict__ rowptr,
                                                         const int32_t* __restrict__ col, int32_t n, int32_t m,
                                                         int32_t* __restrict__ src_out, Ctl* ctl, bool tally) {
+    __shared__ int32_t s_row[kValTile];
     __shared__ int32_t s_r[2];
+    __shared__ int32_t s_wmax[kBlock / 64];
     __shared__ unsigned long long s_work[kBlock / 64];
     if (ctl->err & 15) return;  // rowptr's own checks (bit 16 is this kernel's, set concurrently)
-    // last row i with rowptr[i] <= x, searched in [lo, hi) with rowptr[lo] <= x < rowptr[hi]
-    auto row_of = [&](int32_t x, int32_t lo, int32_t hi) {
+    const int t = threadIdx.x, lane = __lane_id(), wv = t >> 6;
+    const int64_t q0 = (int64_t)blockIdx.x * kValTile;  // < m: the grid covers m exactly
+    const int32_t p0 = (int32_t)q0;
+    const int32_t cnt = (int32_t)min((int64_t)kValTile, (int64_t)m - q0);
+    if (t < 2) {  // last row i with rowptr[i] <= x, with rowptr[lo] <= x < rowptr[hi]
+        const int32_t x = t == 0 ? p0 : p0 + cnt - 1;
+        int32_t lo = 0, hi = n;
         while (hi - lo > 1) {
             const int32_t mid = lo + ((hi - lo) >> 1);
             if (rowptr[mid] <= x) lo = mid;
             else hi = mid;
         }
-        return lo;
-    };
+        s_r[t] = lo;
+    }
+#pragma unroll
+    for (int j = 0; j < kValPer; ++j) s_row[t * kValPer + j] = -1;
+    __syncthreads();
+    const int32_t r0 = s_r[0], r1 = s_r[1];
+    if (t == 0) s_row[0] = r0;
+    for (int32_t r = r0 + 1 + t; r <= r1; r += kBlock) {  // rows starting inside the tile
+        const int32_t q = rowptr[r] - p0;
+        if (q > 0 && q < cnt) atomicMax(&s_row[q], r);
+    }
+    __syncthreads();
+    // inclusive max-scan: 8 slots per lane, then across lanes and waves
+    int32_t v[kValPer];
+    int32_t run = -1;
+#pragma unroll
+    for (int j = 0; j < kValPer; ++j) {
+        run = max(run, s_row[t * kValPer + j]);
+        v[j] = run;
+    }
+    int32_t incl = run;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int32_t u = __shfl_up(incl, o);
+        if (lane >= o) incl = max(incl, u);
+    }
+    if (lane == 63) s_wmax[wv] = incl;
+    __syncthreads();
+    int32_t before = __shfl_up(incl, 1);
+    if (lane == 0) before = -1;
+    for (int i = 0; i < wv; ++i) before = max(before, s_wmax[i]);
+    // the row of the slot before this lane's first (for the first-of-row test)
+    int32_t prev_row = before;
     unsigned long long work = 0ull;
     int bad = 0;
-    for (int c = 0; c < kValChunks; ++c) {
-        const int64_t q0 = ((int64_t)blockIdx.x * kValChunks + c) * kBlock;
-        if (q0 >= m) break;  // workgroup-uniform
-        const int32_t p0 = (int32_t)q0, plast = (int32_t)min(q0 + kBlock, (int64_t)m) - 1;
-        __syncthreads();  // the previous chunk's readers are done with s_r
-        if (threadIdx.x < 2) s_r[threadIdx.x] = row_of(threadIdx.x == 0 ? p0 : plast, 0, n);
-        __syncthreads();
-        const int32_t p = p0 + (int32_t)threadIdx.x;
-        if (p > plast) continue;
-        const int32_t row = row_of(p, s_r[0], s_r[1] + 1);
-        const int32_t prev = p == rowptr[row] ? row : col[p - 1];
-        const int32_t cv = col[p];
-        const bool b = (cv <= prev) | (cv >= n);
-        bad |= b;
-        src_out[p] = row;
-        if (tally && !b) {
-            work += (unsigned long long)(rowptr[row + 1] - p - 1);
-            if (p % kValSpan == 0)
-                work += (unsigned long long)(min(p + kValSpan, m) - p) *
-                        (unsigned long long)(rowptr[cv + 1] - rowptr[cv]);
+#pragma unroll
+    for (int j = 0; j < kValPer; ++j) {
+        const int32_t i = t * kValPer + j;
+        const int32_t row = max(before, v[j]);
+        if (i < cnt) {
+            const int32_t p = p0 + i;
+            const bool first = i == 0 ? rowptr[row] == p : row != prev_row;
+            const int32_t prev = first ? row : col[p - 1];
+            const int32_t cv = col[p];
+            const bool b = (cv <= prev) | (cv >= n);
+            bad |= b;
+            src_out[p] = row;
+            if (tally && !b) {
+                work += (unsigned long long)(rowptr[row + 1] - p - 1);
+                if (p % kValSpan == 0)
+                    work += (unsigned long long)(min(p + kValSpan, m) - p) *
+                            (unsigned long long)(rowptr[cv + 1] - rowptr[cv]);
+            }
         }
+        prev_row = row;
     }
     if (bad) atomicOr(&ctl->err, 16);
     if (tally) {
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) work += __shfl_xor(work, o);
-        if (__lane_id() == 0) s_work[threadIdx.x >> 6] = work;
+        if (lane == 0) s_work[wv] = work;
         __syncthreads();
-        if (threadIdx.x == 0) {
-            unsigned long long t = 0ull;
+        if (t == 0) {
+            unsigned long long tot = 0ull;
 #pragma unroll
-            for (int i = 0; i < kBlock / 64; ++i) t += s_work[i];
-            if (t) atomicAdd(&ctl->merge_work, t);
+            for (int i = 0; i < kBlock / 64; ++i) tot += s_work[i];
+            if (tot) atomicAdd(&ctl->merge_work, tot);
         }
     }
 }
@@ -185,8 +225,8 @@ hipError_t launch_validate(const int32_t* rowptr, const int32_t* col, int32_t n,
     k_ctl_reset<<<1, 64, 0, s>>>(ctl, m);
     k_validate_rowptr<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(rowptr, n, m, ctl);
     if (n > 0 && m > 0)
-        k_validate_rows<<<(unsigned)(((int64_t)m + (int64_t)kValChunks * kBlock - 1) / ((int64_t)kValChunks * kBlock)),
-                          kBlock, 0, s>>>(rowptr, col, n, m, src_out, ctl, tally);
+        k_validate_rows<<<(unsigned)(((int64_t)m + kValTile - 1) / kValTile), kBlock, 0, s>>>(rowptr, col, n, m,
+                                                                                            src_out, ctl, tally);
     return hipGetLastError();
 }
 
