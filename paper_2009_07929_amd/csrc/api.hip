@@ -607,7 +607,21 @@ int32_t state_rounds(const RunSpec& r, Work& w, int p, int32_t m_hint, Ctl& h, h
                 "in-place round");
         int32_t rc = read_ctl(w, h, s);
         if (rc != KTRUSS_OK || h.done) return rc;
-        if (!h.need_support) continue;
+        if (!h.need_support) {
+            // once removed edges fill more than half the buffer, the survivors
+            // move (with their supports) to the other buffer, so that marking
+            // and peeling stop walking them
+            if ((int64_t)2 * h.kept < (int64_t)h.m_buf[p]) {
+                HIP_TRY(launch_compact(w.b[p], w.b[1 - p], &w.c[p], &w.c[1 - p], r.n, 3, r.thr, nullptr, w.batch, w.sc,
+                                       w.ctl, p, m_hint, r.m, PeelSpec{}, s),
+                        "survivor compaction");
+                p ^= 1;
+                rc = read_ctl(w, h, s);
+                if (rc != KTRUSS_OK) return rc;
+                m_hint = h.m_buf[p];
+            }
+            continue;
+        }
         HIP_TRY(launch_compact(w.b[p], w.b[1 - p], &w.c[p], &w.c[1 - p], r.n, 2, r.thr, nullptr, w.batch, w.sc, w.ctl,
                                p, m_hint, r.m, PeelSpec{}, s),
                 "survivor compaction");

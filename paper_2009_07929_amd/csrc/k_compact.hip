@@ -57,6 +57,30 @@ struct CsrRound {
     }
 };
 
+// In-place rounds' compaction (between rounds, after the peel): the alive
+// edges (S >= 0) keep their supports; in the batched form the edges of
+// finished graphs are written to the outputs and leave.
+struct CsrLive {
+    Buf x, y;
+    BatchCtx b;
+    __device__ int32_t load(int32_t e) const { return e; }
+    __device__ bool finished(int32_t e) const { return b.thrv && b.graph_done[b.gidv[x.src[e]]]; }
+    __device__ bool keep(int32_t e) const { return x.S[e] >= 0 && !finished(e); }
+    __device__ void drop(int32_t e, int32_t, int32_t) const {
+        if (x.S[e] >= 0) {  // alive, in a finished graph
+            const int32_t c = x.eid[e];
+            b.mask[c] = 1;
+            b.support[c] = x.S[e];
+        }
+    }
+    __device__ void emit(int32_t e, int32_t, int32_t q) const {
+        y.col[q] = x.col[e];
+        y.src[q] = x.src[e];
+        y.eid[q] = x.eid[e];
+        y.S[q] = x.S[e];
+    }
+};
+
 // CSR element e; keep = the caller's alive flag of its canonical edge.
 struct CsrAlive {
     Buf x, y;
@@ -340,6 +364,15 @@ __device__ __forceinline__ int32_t state_thr(const Buf& x, const BatchCtx& b, in
 }
 __device__ __forceinline__ bool state_dying(int32_t d, int32_t thr) { return d >= 0 && d < thr; }
 
+// Batched form: whether the wave's positions [w0, w1] all lie in one graph
+// that has finished.  Its edges no longer change, so the wave skips them (no
+// read of S, no marks): finished graphs stop costing a pass over their edges.
+__device__ __forceinline__ bool state_wave_done(const Buf& x, const BatchCtx& b, int32_t w0, int32_t w1) {
+    if (!b.thrv || w0 > w1) return false;
+    const int32_t g0 = b.gidv[x.src[w0]], g1 = b.gidv[x.src[w1]];
+    return g0 == g1 && b.graph_done[g0];
+}
+
 __global__ __launch_bounds__(kBlock) void k_state_count(Buf x, BatchCtx b, const Ctl* __restrict__ ctl, int p,
                                                       int32_t thr, int32_t* __restrict__ blockcnt) {
     __shared__ int s_wave[kBlock / 64];
@@ -347,7 +380,11 @@ __global__ __launch_bounds__(kBlock) void k_state_count(Buf x, BatchCtx b, const
     int32_t lo, hi;
     chunk_of(ctl->m_buf[p], lo, hi);
     int c = 0;
-    for (int32_t i = lo + (int32_t)threadIdx.x; i < hi; i += kBlock) c += state_dying(x.S[i], state_thr(x, b, thr, i));
+    for (int32_t i = lo + (int32_t)threadIdx.x; i < hi; i += kBlock) {
+        const int32_t w0 = i - __lane_id();
+        if (state_wave_done(x, b, w0, min(w0 + 63, hi - 1))) continue;
+        c += state_dying(x.S[i], state_thr(x, b, thr, i));
+    }
     c = block_sum<kBlock>(c, s_wave);
     if (threadIdx.x == 0) blockcnt[blockIdx.x] = c;
 }
@@ -372,9 +409,11 @@ __global__ __launch_bounds__(kBlock) void k_state_scatter(Buf x, BatchCtx b, con
     const int lane = __lane_id();
     for (int32_t t0 = lo; t0 < hi; t0 += kBlock) {
         const int32_t i = t0 + (int32_t)threadIdx.x;
-        const int32_t d = i < hi ? x.S[i] : kDead;
-        const bool k = i < hi && state_dying(d, state_thr(x, b, thr, i));
-        if (b.thrv) {
+        const int32_t w0 = i - lane;
+        const bool gone = state_wave_done(x, b, w0, min(w0 + 63, hi - 1));
+        const int32_t d = i < hi && !gone ? x.S[i] : kDead;
+        const bool k = i < hi && !gone && state_dying(d, state_thr(x, b, thr, i));
+        if (b.thrv && !gone) {
             // per-graph counts of the removed edges: a graph's edges are
             // consecutive, so a segmented sum over the wave gives one atomic
             // per graph piece
@@ -400,7 +439,7 @@ __global__ __launch_bounds__(kBlock) void k_state_scatter(Buf x, BatchCtx b, con
         // the round's liveness words (i is the first of its wave's 64 positions on lane 0)
         const unsigned long long dead = __ballot(i < hi && (d == kDead || d == kDying));
         const unsigned long long dying = __ballot(k);
-        if (__lane_id() == 0 && i < hi) livew[i >> 6] = LiveWord{dead, dying};
+        if (__lane_id() == 0 && i < hi && !gone) livew[i >> 6] = LiveWord{dead, dying};
         base += tot;
     }
 }
@@ -460,7 +499,7 @@ hipError_t launch_state_mark(const Buf& x, const BatchCtx& b, int32_t G, int32_t
 hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* cy, int32_t n, int mode, int32_t thr,
                           const uint8_t* alive_can, const BatchCtx& b, Scratch& sc, Ctl* ctl, int p, int32_t m_hint,
                           int32_t csc_hint, const PeelSpec& peel, hipStream_t s) {
-    const int round = mode != 1;
+    const int round = mode != 1;  // modes 0, 2, 3 skip their work once the run is done
     const bool batch = b.thrv != nullptr;
     const bool inc = peel.on && mode == 0 && cx;
     if (mode == 0) {
@@ -469,6 +508,8 @@ hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* 
     } else if (mode == 2) {
         run_filter(CsrRound{x, y, thr, b, nullptr}, ctl, p, 2, 1, sc.blockcnt, sc.blockoff, sc.xscan, sc.keepw,
                    m_hint, s);
+    } else if (mode == 3) {
+        run_filter(CsrLive{x, y, b}, ctl, p, 2, 1, sc.blockcnt, sc.blockoff, sc.xscan, sc.keepw, m_hint, s);
     } else {
         run_filter(CsrAlive{x, y, alive_can}, ctl, p, 2, 0, sc.blockcnt, sc.blockoff, sc.xscan, sc.keepw, m_hint, s);
     }

@@ -25,7 +25,9 @@ hipError_t launch_prune_canonical(const int32_t* support, uint8_t* alive, int32_
 // mode 0: keep = S[e] >= thr (a prune round: updates the pass count and the
 // fixpoint flag); mode 1: keep = alive_can[eid[e]] != 0 (restriction to a
 // caller's alive set); mode 2: keep = S[e] >= thr without the round's
-// bookkeeping (the survivors of in-place rounds, before a recomputation).
+// bookkeeping (the survivors of in-place rounds, before a recomputation);
+// mode 3: keep = S[e] >= 0 with the supports (in-place rounds shedding their
+// removed edges, and in the batched form writing out finished graphs).
 // The in-edge lists are compacted too when cx, cy are given.
 // With a batch context (b.thrv set) the threshold is per vertex, edges of
 // graphs finished in this pass are written to the outputs and dropped, and
