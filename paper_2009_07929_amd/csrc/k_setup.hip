@@ -54,9 +54,11 @@ __global__ __launch_bounds__(kBlock) void k_validate_rowptr(const int32_t* __res
 constexpr int kValSpan = 16;
 constexpr int kValPer = 8;
 constexpr int kValTile = kBlock * kValPer;
+constexpr int kValMaxGrid = 2048;  // workgroups (tiles strided over them)
 
 // tally: also accumulates the input statistic of the light-graph gate into
-// ctl->merge_work: the tail of every edge's row after it, exactly, plus the
+// ctl->merge_work: the tail of every edge's row after it, exactly (summed per
+// row as d (d - 1) / 2 by the tile holding the row's first edge), plus the
 // length of row kappa (the edge's column) sampled on every edge whose position
 // is a multiple of kValSpan and weighted by the edge count of that span.
 __global__ __launch_bounds__(kBlock) void k_validate_rows(const int32_t* __restrict__ rowptr,
@@ -68,72 +70,82 @@ __global__ __launch_bounds__(kBlock) void k_validate_rows(const int32_t* __restr
     __shared__ unsigned long long s_work[kBlock / 64];
     if (ctl->err & 15) return;  // rowptr's own checks (bit 16 is this kernel's, set concurrently)
     const int t = threadIdx.x, lane = __lane_id(), wv = t >> 6;
-    const int64_t q0 = (int64_t)blockIdx.x * kValTile;  // < m: the grid covers m exactly
-    const int32_t p0 = (int32_t)q0;
-    const int32_t cnt = (int32_t)min((int64_t)kValTile, (int64_t)m - q0);
-    if (t < 2) {  // last row i with rowptr[i] <= x, with rowptr[lo] <= x < rowptr[hi]
-        const int32_t x = t == 0 ? p0 : p0 + cnt - 1;
-        int32_t lo = 0, hi = n;
-        while (hi - lo > 1) {
-            const int32_t mid = lo + ((hi - lo) >> 1);
-            if (rowptr[mid] <= x) lo = mid;
-            else hi = mid;
-        }
-        s_r[t] = lo;
-    }
-#pragma unroll
-    for (int j = 0; j < kValPer; ++j) s_row[t * kValPer + j] = -1;
-    __syncthreads();
-    const int32_t r0 = s_r[0], r1 = s_r[1];
-    if (t == 0) s_row[0] = r0;
-    for (int32_t r = r0 + 1 + t; r <= r1; r += kBlock) {  // rows starting inside the tile
-        const int32_t q = rowptr[r] - p0;
-        if (q > 0 && q < cnt) atomicMax(&s_row[q], r);
-    }
-    __syncthreads();
-    // inclusive max-scan: 8 slots per lane, then across lanes and waves
-    int32_t v[kValPer];
-    int32_t run = -1;
-#pragma unroll
-    for (int j = 0; j < kValPer; ++j) {
-        run = max(run, s_row[t * kValPer + j]);
-        v[j] = run;
-    }
-    int32_t incl = run;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        const int32_t u = __shfl_up(incl, o);
-        if (lane >= o) incl = max(incl, u);
-    }
-    if (lane == 63) s_wmax[wv] = incl;
-    __syncthreads();
-    int32_t before = __shfl_up(incl, 1);
-    if (lane == 0) before = -1;
-    for (int i = 0; i < wv; ++i) before = max(before, s_wmax[i]);
-    // the row of the slot before this lane's first (for the first-of-row test)
-    int32_t prev_row = before;
     unsigned long long work = 0ull;
     int bad = 0;
+    // tiles strided over the grid: one atomic per workgroup for the statistic
+    for (int64_t q0 = (int64_t)blockIdx.x * kValTile; q0 < m; q0 += (int64_t)gridDim.x * kValTile) {
+        const int32_t p0 = (int32_t)q0;
+        const int32_t cnt = (int32_t)min((int64_t)kValTile, (int64_t)m - q0);
+        __syncthreads();  // the previous tile is done with s_row, s_r and s_wmax
+        if (t < 2) {      // last row i with rowptr[i] <= x, with rowptr[lo] <= x < rowptr[hi]
+            const int32_t x = t == 0 ? p0 : p0 + cnt - 1;
+            int32_t lo = 0, hi = n;
+            while (hi - lo > 1) {
+                const int32_t mid = lo + ((hi - lo) >> 1);
+                if (rowptr[mid] <= x) lo = mid;
+                else hi = mid;
+            }
+            s_r[t] = lo;
+        }
 #pragma unroll
-    for (int j = 0; j < kValPer; ++j) {
-        const int32_t i = t * kValPer + j;
-        const int32_t row = max(before, v[j]);
-        if (i < cnt) {
-            const int32_t p = p0 + i;
-            const bool first = i == 0 ? rowptr[row] == p : row != prev_row;
-            const int32_t prev = first ? row : col[p - 1];
-            const int32_t cv = col[p];
-            const bool b = (cv <= prev) | (cv >= n);
-            bad |= b;
-            src_out[p] = row;
-            if (tally && !b) {
-                work += (unsigned long long)(rowptr[row + 1] - p - 1);
-                if (p % kValSpan == 0)
+        for (int j = 0; j < kValPer; ++j) s_row[t * kValPer + j] = -1;
+        __syncthreads();
+        const int32_t r0 = s_r[0], r1 = s_r[1];
+        if (t == 0) {
+            s_row[0] = r0;
+            if (tally && rowptr[r0] == p0) {  // the statistic's tail part, per row: sum of its tails d (d - 1) / 2
+                const uint64_t d = (uint64_t)(rowptr[r0 + 1] - p0);
+                work += d * (d - 1) / 2;
+            }
+        }
+        for (int32_t r = r0 + 1 + t; r <= r1; r += kBlock) {  // rows starting inside the tile
+            const int32_t q = rowptr[r] - p0;
+            if (q > 0 && q < cnt) atomicMax(&s_row[q], r);
+            if (tally) {
+                const uint64_t d = (uint64_t)(rowptr[r + 1] - rowptr[r]);
+                work += d * (d - 1) / 2;
+            }
+        }
+        __syncthreads();
+        // inclusive max-scan: 8 slots per lane, then across lanes and waves
+        int32_t v[kValPer];
+        int32_t run = -1;
+#pragma unroll
+        for (int j = 0; j < kValPer; ++j) {
+            run = max(run, s_row[t * kValPer + j]);
+            v[j] = run;
+        }
+        int32_t incl = run;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t u = __shfl_up(incl, o);
+            if (lane >= o) incl = max(incl, u);
+        }
+        if (lane == 63) s_wmax[wv] = incl;
+        __syncthreads();
+        int32_t before = __shfl_up(incl, 1);
+        if (lane == 0) before = -1;
+        for (int i = 0; i < wv; ++i) before = max(before, s_wmax[i]);
+        // the row of the slot before this lane's first (for the first-of-row test)
+        int32_t prev_row = before;
+#pragma unroll
+        for (int j = 0; j < kValPer; ++j) {
+            const int32_t i = t * kValPer + j;
+            const int32_t row = max(before, v[j]);
+            if (i < cnt) {
+                const int32_t p = p0 + i;
+                const bool first = i == 0 ? rowptr[row] == p : row != prev_row;
+                const int32_t prev = first ? row : col[p - 1];
+                const int32_t cv = col[p];
+                const bool b = (cv <= prev) | (cv >= n);
+                bad |= b;
+                src_out[p] = row;
+                if (tally && !b && p % kValSpan == 0)
                     work += (unsigned long long)(min(p + kValSpan, m) - p) *
                             (unsigned long long)(rowptr[cv + 1] - rowptr[cv]);
             }
+            prev_row = row;
         }
-        prev_row = row;
     }
     if (bad) atomicOr(&ctl->err, 16);
     if (tally) {
@@ -225,8 +237,8 @@ hipError_t launch_validate(const int32_t* rowptr, const int32_t* col, int32_t n,
     k_ctl_reset<<<1, 64, 0, s>>>(ctl, m);
     k_validate_rowptr<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(rowptr, n, m, ctl);
     if (n > 0 && m > 0)
-        k_validate_rows<<<(unsigned)(((int64_t)m + kValTile - 1) / kValTile), kBlock, 0, s>>>(rowptr, col, n, m,
-                                                                                            src_out, ctl, tally);
+        k_validate_rows<<<(unsigned)min(((int64_t)m + kValTile - 1) / kValTile, (int64_t)kValMaxGrid), kBlock, 0,
+                          s>>>(rowptr, col, n, m, src_out, ctl, tally);
     return hipGetLastError();
 }
 
