@@ -82,7 +82,9 @@ struct Ctl {
     int32_t csc_pack;    // the lists are being packed in this round (tombstones dominate)
     int32_t csc_next;    // entries after packing
     int32_t need_support; // incremental maintenance skipped its peel: the next round recomputes supports
-    int32_t front_n;      // edges removed by the current in-place prune (incremental maintenance)
+    int32_t front_n;      // edges an in-place prune lists for the peel (removed with support > 0)
+    int32_t removed_now;  // edges the in-place prune removes (the listed ones and those in no triangle)
+    int32_t pad_;
     int64_t removed_total;
     unsigned long long merge_work;  // input's merge length summed over its edges (row tail + row kappa)
 };

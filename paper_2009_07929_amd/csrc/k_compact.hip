@@ -373,28 +373,49 @@ __device__ __forceinline__ bool state_wave_done(const Buf& x, const BatchCtx& b,
     return g0 == g1 && b.graph_done[g0];
 }
 
+// A removed edge with support 0 lies in no triangle of the round's graph, so
+// it destroys none: it is marked but not listed for the peel.
+__device__ __forceinline__ bool state_listed(int32_t d) { return d > 0; }
+
+// Per workgroup chunk: the removed edges (blockcnt2) and those listed for the
+// peel (blockcnt, scanned into frontier positions).
 __global__ __launch_bounds__(kBlock) void k_state_count(Buf x, BatchCtx b, const Ctl* __restrict__ ctl, int p,
-                                                      int32_t thr, int32_t* __restrict__ blockcnt) {
+                                                      int32_t thr, int32_t* __restrict__ blockcnt,
+                                                      int32_t* __restrict__ blockcnt2) {
     __shared__ int s_wave[kBlock / 64];
     if (ctl->done) return;
     int32_t lo, hi;
     chunk_of(ctl->m_buf[p], lo, hi);
-    int c = 0;
+    int c = 0, r = 0;
     for (int32_t i = lo + (int32_t)threadIdx.x; i < hi; i += kBlock) {
         const int32_t w0 = i - __lane_id();
         if (state_wave_done(x, b, w0, min(w0 + 63, hi - 1))) continue;
-        c += state_dying(x.S[i], state_thr(x, b, thr, i));
+        const int32_t d = x.S[i];
+        const bool k = state_dying(d, state_thr(x, b, thr, i));
+        r += k;
+        c += k && state_listed(d);
     }
     c = block_sum<kBlock>(c, s_wave);
-    if (threadIdx.x == 0) blockcnt[blockIdx.x] = c;
+    r = block_sum<kBlock>(r, s_wave);
+    if (threadIdx.x == 0) {
+        blockcnt[blockIdx.x] = c;
+        blockcnt2[blockIdx.x] = r;
+    }
 }
 
 __global__ __launch_bounds__(kScanThreads) void k_state_scan(const int32_t* __restrict__ blockcnt,
+                                                           const int32_t* __restrict__ blockcnt2,
                                                            int32_t* __restrict__ blockoff, int32_t G, Ctl* ctl) {
     __shared__ int s_wave[kScanThreads / 64];
     if (ctl->done) return;
     const int total = scan_block_counts(blockcnt, blockoff, G, s_wave);
-    if (threadIdx.x == 0) ctl->front_n = total;
+    int removed = 0;
+    for (int32_t j = (int32_t)threadIdx.x; j < G; j += kScanThreads) removed += blockcnt2[j];
+    removed = block_sum<kScanThreads>(removed, s_wave);
+    if (threadIdx.x == 0) {
+        ctl->front_n = total;
+        ctl->removed_now = removed;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_state_scatter(Buf x, BatchCtx b, const Ctl* __restrict__ ctl, int p,
@@ -412,13 +433,14 @@ __global__ __launch_bounds__(kBlock) void k_state_scatter(Buf x, BatchCtx b, con
         const int32_t w0 = i - lane;
         const bool gone = state_wave_done(x, b, w0, min(w0 + 63, hi - 1));
         const int32_t d = i < hi && !gone ? x.S[i] : kDead;
-        const bool k = i < hi && !gone && state_dying(d, state_thr(x, b, thr, i));
+        const bool kr = i < hi && !gone && state_dying(d, state_thr(x, b, thr, i));  // removed
+        const bool k = kr && state_listed(d);                                          // listed for the peel
         if (b.thrv && !gone) {
             // per-graph counts of the removed edges: a graph's edges are
             // consecutive, so a segmented sum over the wave gives one atomic
             // per graph piece
             const int32_t key = i < hi ? b.gidv[x.src[i]] : -1;
-            int32_t v = k ? 1 : 0;
+            int32_t v = kr ? 1 : 0;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
                 const int32_t u = __shfl_up(v, o);
@@ -430,15 +452,15 @@ __global__ __launch_bounds__(kBlock) void k_state_scatter(Buf x, BatchCtx b, con
         }
         int tot;
         const int32_t q = base + block_excl_flag<kBlock>(k, s_wave, tot);
-        if (k) {
+        if (kr) {
             x.S[i] = kDying;
-            frontier[q] = i;
+            if (k) frontier[q] = i;
         } else if (d == kDying) {
             x.S[i] = kDead;
         }
         // the round's liveness words (i is the first of its wave's 64 positions on lane 0)
         const unsigned long long dead = __ballot(i < hi && (d == kDead || d == kDying));
-        const unsigned long long dying = __ballot(k);
+        const unsigned long long dying = __ballot(kr);
         if (__lane_id() == 0 && i < hi && !gone) livew[i >> 6] = LiveWord{dead, dying};
         base += tot;
     }
@@ -488,8 +510,8 @@ __global__ __launch_bounds__(kBlock) void k_state_graphs(BatchCtx b, int32_t G, 
 hipError_t launch_state_mark(const Buf& x, const BatchCtx& b, int32_t G, int32_t thr, int32_t* frontier, Scratch& sc,
                              Ctl* ctl, int p, int32_t m_hint, hipStream_t s) {
     const int32_t grid = filter_grid(m_hint);
-    k_state_count<<<grid, kBlock, 0, s>>>(x, b, ctl, p, thr, sc.blockcnt);
-    k_state_scan<<<1, kScanThreads, 0, s>>>(sc.blockcnt, sc.blockoff, grid, ctl);
+    k_state_count<<<grid, kBlock, 0, s>>>(x, b, ctl, p, thr, sc.blockcnt, sc.blockcnt2);
+    k_state_scan<<<1, kScanThreads, 0, s>>>(sc.blockcnt, sc.blockcnt2, sc.blockoff, grid, ctl);
     k_state_scatter<<<grid, kBlock, 0, s>>>(x, b, ctl, p, thr, sc.blockoff, frontier,
                                             reinterpret_cast<LiveWord*>(sc.keepw));
     if (b.thrv && G > 0) k_state_graphs<<<grid_for(G), kBlock, 0, s>>>(b, G, ctl);

@@ -134,18 +134,20 @@ __global__ __launch_bounds__(kBlock) void k_peel(Buf x, Buf y, Csc c, const Keep
 
 // One thread: the round's bookkeeping (pass count, fixpoint, survivors) and,
 // with ratio > 0, whether the frontier is left to a recomputation.
+// The peel's work is the listed frontier; removed edges in no triangle cost
+// it nothing, so the comparison with ratio x the survivors counts the listed.
 __global__ void k_state_decide(Ctl* ctl, int p, float ratio) {
     if (threadIdx.x != 0 || blockIdx.x != 0 || ctl->done) return;
-    const int32_t nf = ctl->front_n;
+    const int32_t removed = ctl->removed_now, nf = ctl->front_n;
     ctl->rounds += 1;
     ctl->need_support = 0;
-    if (nf == 0) {
+    if (removed == 0) {
         ctl->done = 1;
         ctl->final_buf = p;
         return;
     }
-    ctl->kept -= nf;
-    ctl->removed_total += nf;
+    ctl->kept -= removed;
+    ctl->removed_total += removed;
     if (ratio > 0.f && (double)nf > (double)ratio * (double)ctl->kept) ctl->need_support = 1;
 }
 
