@@ -92,6 +92,8 @@ FullLayout full_layout(int32_t n, int64_t m, int32_t G) {
     L.hwoff = take(sizeof(int64_t) * ((size_t)n + 1));
     L.wave_tasks = take(em);
     L.thread_tasks = take(em);
+    L.long_off = take(vn);
+    L.long_rows = take(vn);
     L.ctl = take(sizeof(Ctl));
     if (G > 0) {
         F.gidv = take(vn);
@@ -154,6 +156,8 @@ Work carve(void* work, int32_t n, int64_t m, int32_t G) {
     w.sc.hit_cap = (int64_t)kHitWordsPerEdge * m;
     w.sc.wave_tasks = (int32_t*)(base + L.wave_tasks);
     w.sc.thread_tasks = (int32_t*)(base + L.thread_tasks);
+    w.sc.long_off = (int32_t*)(base + L.long_off);
+    w.sc.long_rows = (int32_t*)(base + L.long_rows);
     w.ctl = (Ctl*)(base + L.ctl);
     if (G > 0) {
         w.batch.gidv = (int32_t*)(base + F.gidv);

@@ -84,7 +84,7 @@ struct Ctl {
     int32_t need_support; // incremental maintenance skipped its peel: the next round recomputes supports
     int32_t front_n;      // edges an in-place prune lists for the peel (removed with support > 0)
     int32_t removed_now;  // edges the in-place prune removes (the listed ones and those in no triangle)
-    int32_t pad_;
+    int32_t n_long;       // rows whose hit words are summed per row (k_hit_sum_long) in the current pass
     int64_t removed_total;
     unsigned long long merge_work;  // input's merge length summed over its edges (row tail + row kappa)
 };
@@ -164,7 +164,15 @@ struct Scratch {
     int64_t hit_cap;           // words of hitw (kHitWordsPerEdge * m)
     int32_t* wave_tasks;  // int32[m]
     int32_t* thread_tasks;// int32[m]
+    int32_t* long_off;    // int32[n+1]: scan of the rows whose hit words are summed per row
+    int32_t* long_rows;   // int32[n]: those rows
 };
+
+// Rows whose length d lies in (kHitLongMin, kHitLongMax] have their hit words
+// summed by one workgroup per row (every word read once, counts in LDS); the
+// others by windows of 64 positions.
+constexpr int32_t kHitLongMin = 192;
+constexpr int32_t kHitLongMax = 4096;
 
 // Batched form: per-vertex graph id and threshold, per-graph state, outputs.
 // thrv == nullptr means a single graph (the scalar threshold applies).
@@ -200,7 +208,7 @@ struct Layout {
     size_t cedge, csrc, ckey, cptr;
     size_t xscan, keepw, cxscan, blockcnt, blockoff, blockcnt2, blockoff2, alive_in, itemoff, items, ctail,
         is_hub, hub_row, hitw, hwoff, wave_tasks, thread_tasks, insum, cycles, act_off, act_list, feats, pred, chunk_sz,
-        rs_hist;
+        rs_hist, long_off, long_rows;
     size_t ctl;        // Ctl
     size_t total;
 };

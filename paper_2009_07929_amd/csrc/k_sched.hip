@@ -404,6 +404,22 @@ __global__ __launch_bounds__(kBlock) void k_hub_items(HubChunks f, const int32_t
 
 // Rows kappa that carry support work in the current pass (in-edges and a
 // non-empty row).
+// Rows whose hit words k_hit_sum_long sums.
+struct LongRow {
+    const int32_t* rowptr;
+    __device__ int32_t operator()(int32_t i) const {
+        const int32_t d = rowptr[i + 1] - rowptr[i];
+        return (d > kHitLongMin && d <= kHitLongMax) ? 1 : 0;
+    }
+};
+
+__global__ __launch_bounds__(kBlock) void k_long_list(LongRow f, int32_t n, const int32_t* __restrict__ off,
+                                                    int32_t* __restrict__ list, const Ctl* __restrict__ ctl) {
+    if (ctl->done) return;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n && f((int32_t)i)) list[off[i]] = (int32_t)i;
+}
+
 struct ActiveRow {
     const int32_t* rowptr;
     const int32_t* alive_in;  // alive in-edges per row
@@ -755,6 +771,9 @@ hipError_t launch_prepare_pass(const Buf& x, const Csc& c, int32_t n, int sched,
         k_task_tails<<<min(grid_for(m0), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, c, ctl, sc.ctail);
     // first hit word of every row's tasks (a 64-bit scan of the rows' word counts)
     device_scan64(RowWords{x.rowptr}, n, ctl, sc, sc.hwoff, s);
+    // the rows whose hit words are summed per row
+    device_scan(LongRow{x.rowptr}, n, ctl, sc, sc.long_off, &ctl->n_long, s);
+    if (n > 0) k_long_list<<<grid_for(n), kBlock, 0, s>>>(LongRow{x.rowptr}, n, sc.long_off, sc.long_rows, ctl);
     if (sched == kSchedSampleWave) {  // cost sampling: no hub rows, every task on the wavefront kernel
         k_fill_u8<<<grid_for(n), kBlock, 0, s>>>(sc.is_hub, n, 0);
         is_hub = sc.is_hub;

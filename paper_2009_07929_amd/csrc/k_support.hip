@@ -115,6 +115,9 @@ __device__ __forceinline__ void wave_task(const Buf& x, int32_t e, unsigned long
     if (cycles && lane == 0) atomicAdd(&cycles[k], (unsigned long long)clock64() - t0);
 }
 
+constexpr int kHitLongGrid = 2048;  // workgroups of k_hit_sum_long (rows strided over them)
+constexpr int kHitLongUnroll = 4;   // word steps whose loads k_hit_sum_long issues together
+
 // ------------------------------------------------- workgroup-per-hub-row
 // One workgroup per hub item: row kappa of A22 and up to kHubChunk of the
 // tasks that select it.  Row kappa is staged once in LDS as a rank bitmap over
@@ -438,11 +441,14 @@ __global__ __launch_bounds__(kBlock) void k_hit_sum(Buf x, const unsigned long l
     const int32_t P0 = (int32_t)P0l;
     const int32_t* __restrict__ col = x.col;
     const int32_t p = P0 + lane;
+    // rows summed by k_hit_sum_long are left out here (their tasks hit only their own row)
+    auto is_long = [](int32_t d) { return d > kHitLongMin && d <= kHitLongMax; };
     unsigned long long v = 0;
     if (p < m && lane < 63) {  // position P0 + lane + 1 is tail offset 0 of task p
         const int32_t i = x.src[p];
-        const int32_t L = x.rowptr[i + 1] - p - 1;
-        if (L > 0 && hub_row[col[p]]) {
+        const int32_t re = x.rowptr[i + 1];
+        const int32_t L = re - p - 1;
+        if (L > 0 && !is_long(re - x.rowptr[i]) && hub_row[col[p]]) {
             const int64_t w = hwoff[i + 1] - hit_words_upto(L);
             if (w < hit_cap) v = hitw[w] << (lane + 1);
         }
@@ -450,7 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_hit_sum(Buf x, const unsigned long l
     uint32_t add = (uint32_t)__popcll(transpose64(v, lane));
     const int32_t r0 = x.src[P0];  // the row holding P0
     const int32_t r0s = x.rowptr[r0], r0e = x.rowptr[r0 + 1];
-    if (r0s < P0) {
+    if (r0s < P0 && !is_long(r0e - r0s)) {
         const int64_t rend = hwoff[r0 + 1];
         for (int32_t j0 = r0s; j0 < P0; j0 += 64) {
             const int32_t j = j0 + lane;
@@ -468,6 +474,73 @@ __global__ __launch_bounds__(kBlock) void k_hit_sum(Buf x, const unsigned long l
         }
     }
     if (p < m && add) x.S[p] += (int32_t)add;
+}
+
+// Row-local sum of the hit words of one row per workgroup, for rows of length
+// d in (kHitLongMin, kHitLongMax], where the windows above would re-read the
+// words of a row's earlier tasks once per window.  The row's tasks are taken 64
+// at a time (task r = 64 b + lane, relative to the row start); for word c of
+// every task of the block, the bits that fall in window b + c (relative
+// positions 64 (b + c) ...) and those that spill into window b + c + 1 are
+// separated by two shifts, and a 64x64 bit transpose plus a popcount of each
+// gives every position of the two windows its count, added in LDS.  The spill
+// of word c is carried in a register into the next step, so every word is read
+// once and transposed once.  The counts are then added to S(i, w).
+__global__ __launch_bounds__(kBlock) void k_hit_sum_long(Buf x, const unsigned long long* __restrict__ hitw,
+                                                       const int64_t* __restrict__ hwoff, int64_t hit_cap,
+                                                       const uint8_t* __restrict__ hub_row,
+                                                       const int32_t* __restrict__ long_rows,
+                                                       const Ctl* __restrict__ ctl) {
+    __shared__ int32_t s_cnt[kHitLongMax + 64 * (kHitLongUnroll + 1)];
+    if (ctl->done) return;
+    const int32_t nl = ctl->n_long;
+    const int t = threadIdx.x, lane = __lane_id(), wv = t >> 6;
+    const int32_t* __restrict__ col = x.col;
+    for (int32_t k = (int32_t)blockIdx.x; k < nl; k += (int32_t)gridDim.x) {
+        const int32_t i = long_rows[k];
+        const int32_t rs = x.rowptr[i], d = x.rowptr[i + 1] - rs;  // kHitLongMin < d <= kHitLongMax
+        const int64_t rend = hwoff[i + 1];
+        for (int32_t j = t; j < d + 64; j += kBlock) s_cnt[j] = 0;
+        __syncthreads();
+        const int32_t nb = (d + 63) >> 6;
+        for (int32_t b = wv; b < nb; b += kBlock / 64) {
+            const int32_t r = 64 * b + lane;
+            int32_t nw = 0;
+            int64_t w0 = 0;
+            if (r < d) {
+                const int32_t L = d - 1 - r;
+                if (L > 0 && hub_row[col[rs + r]]) {
+                    nw = (L + 63) >> 6;
+                    w0 = rend - hit_words_upto(L);
+                }
+            }
+            // the block's first task has the longest tail: its word count bounds the steps;
+            // window b + c takes the low part of word c and the spill of word c - 1
+            const int32_t steps = (d - 1 - 64 * b + 63) >> 6;
+            unsigned long long prev = 0ull;
+            for (int32_t c0 = 0; c0 <= steps; c0 += kHitLongUnroll) {
+                unsigned long long wd[kHitLongUnroll];
+#pragma unroll
+                for (int u = 0; u < kHitLongUnroll; ++u) {  // the step group's loads first
+                    const int32_t c = c0 + u;
+                    wd[u] = (c < nw && w0 + c < hit_cap) ? hitw[w0 + c] : 0ull;  // past the capacity: added directly
+                }
+#pragma unroll
+                for (int u = 0; u < kHitLongUnroll; ++u) {
+                    const unsigned long long v = (lane == 63 ? 0ull : (wd[u] << (lane + 1))) | (prev >> (63 - lane));
+                    prev = wd[u];
+                    const uint32_t cnt = (uint32_t)__popcll(transpose64(v, lane));
+                    if (cnt) atomicAdd(&s_cnt[64 * (b + c0 + u) + lane], (int32_t)cnt);
+                }
+            }
+        }
+        __syncthreads();
+        for (int32_t j = t; j < d; j += kBlock) {
+            const int32_t a = s_cnt[j];
+            if (a) x.S[rs + j] += a;
+        }
+        __syncthreads();  // the next row clears s_cnt
+    }
 }
 
 // Measurement aid (profiling only): statistics of the pass just computed,
@@ -547,6 +620,7 @@ hipError_t launch_hit_sum(const Buf& x, const Scratch& sc, const int32_t* m_coun
     const int64_t windows = ((int64_t)m_hint + 63) / 64;
     const unsigned grid = (unsigned)((windows + kBlock / 64 - 1) / (kBlock / 64));  // one wave per window
     k_hit_sum<<<grid, kBlock, 0, s>>>(x, sc.hitw, sc.hwoff, sc.hit_cap, sc.hub_row, m_count, ctl);
+    k_hit_sum_long<<<kHitLongGrid, kBlock, 0, s>>>(x, sc.hitw, sc.hwoff, sc.hit_cap, sc.hub_row, sc.long_rows, ctl);
     return hipGetLastError();
 }
 
