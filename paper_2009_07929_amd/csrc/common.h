@@ -60,10 +60,9 @@ enum PassStat {
 
 // Device-resident control block of one run.  Buffer b of the double-buffered
 // working graph holds m_buf[b] alive edges.
-// Support values of edges that in-place rounds have removed (alive edges
-// hold their support, >= 0).
-constexpr int32_t kDead = -1;   // removed by an earlier round
-constexpr int32_t kDying = -2;  // removed by the current round
+// Support value of an edge that an in-place round has removed (alive edges
+// hold their support, >= 0); which round removed it is in the liveness words.
+constexpr int32_t kDying = -2;
 
 struct Ctl {
     int32_t m_buf[2];
@@ -130,7 +129,9 @@ struct alignas(16) KeepWord {
 
 // Liveness of an in-place round, 64 positions to a word: removed by an
 // earlier round (dead) or by this one (dying).  Same size as a KeepWord, and
-// kept in the same scratch (the two are never live at once).
+// kept in the same scratch (the two are never live at once).  Words of waves
+// that lie in a finished graph (batched form) say nothing useful: no peel
+// reaches those positions.
 struct alignas(16) LiveWord {
     unsigned long long dead;
     unsigned long long dying;

@@ -378,22 +378,48 @@ __device__ __forceinline__ bool state_wave_done(const Buf& x, const BatchCtx& b,
 __device__ __forceinline__ bool state_listed(int32_t d) { return d > 0; }
 
 // Per workgroup chunk: the removed edges (blockcnt2) and those listed for the
-// peel (blockcnt, scanned into frontier positions).
+// peel (blockcnt, scanned into frontier positions).  This pass reads every
+// support once and writes the round's liveness words (removed earlier: S < 0;
+// removed now), which the scatter then reads instead of the supports; in the
+// batched form it also counts each graph's removed edges.
 __global__ __launch_bounds__(kBlock) void k_state_count(Buf x, BatchCtx b, const Ctl* __restrict__ ctl, int p,
                                                       int32_t thr, int32_t* __restrict__ blockcnt,
-                                                      int32_t* __restrict__ blockcnt2) {
+                                                      int32_t* __restrict__ blockcnt2,
+                                                      LiveWord* __restrict__ livew) {
     __shared__ int s_wave[kBlock / 64];
     if (ctl->done) return;
     int32_t lo, hi;
     chunk_of(ctl->m_buf[p], lo, hi);
+    const int lane = __lane_id();
     int c = 0, r = 0;
-    for (int32_t i = lo + (int32_t)threadIdx.x; i < hi; i += kBlock) {
-        const int32_t w0 = i - __lane_id();
-        if (state_wave_done(x, b, w0, min(w0 + 63, hi - 1))) continue;
-        const int32_t d = x.S[i];
-        const bool k = state_dying(d, state_thr(x, b, thr, i));
-        r += k;
-        c += k && state_listed(d);
+    for (int32_t t0 = lo; t0 < hi; t0 += kBlock) {
+        const int32_t i = t0 + (int32_t)threadIdx.x;
+        const int32_t w0 = i - lane;  // the wave's first position (a multiple of 64)
+        // a wave inside one finished graph reads nothing and removes nothing
+        const bool gone = state_wave_done(x, b, w0, min(w0 + 63, hi - 1));
+        const int32_t d = i < hi && !gone ? x.S[i] : kDying;
+        const bool kr = i < hi && !gone && state_dying(d, state_thr(x, b, thr, i));  // removed
+        const bool k = kr && state_listed(d);                                          // listed for the peel
+        r += kr;
+        c += k;
+        if (b.thrv && !gone) {
+            // per-graph counts of the removed edges: a graph's edges are
+            // consecutive, so a segmented sum over the wave gives one atomic
+            // per graph piece
+            const int32_t key = i < hi ? b.gidv[x.src[i]] : -1;
+            int32_t v = kr ? 1 : 0;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int32_t u = __shfl_up(v, o);
+                const int32_t kk = __shfl_up(key, o);
+                if (lane >= o && kk == key) v += u;
+            }
+            const int32_t next = __shfl_down(key, 1);
+            if (i < hi && v && (lane == 63 || next != key)) atomicAdd(&b.low_cnt[key], v);
+        }
+        const unsigned long long dead = __ballot(i < hi && d < 0);
+        const unsigned long long dying = __ballot(kr);
+        if (lane == 0 && w0 < hi) livew[w0 >> 6] = LiveWord{dead, dying};
     }
     c = block_sum<kBlock>(c, s_wave);
     r = block_sum<kBlock>(r, s_wave);
@@ -418,10 +444,12 @@ __global__ __launch_bounds__(kScanThreads) void k_state_scan(const int32_t* __re
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_state_scatter(Buf x, BatchCtx b, const Ctl* __restrict__ ctl, int p,
-                                                        int32_t thr, const int32_t* __restrict__ blockoff,
+// The removed edges of the round (from the liveness words) get S = kDying and
+// the listed ones their frontier slots, in position order.
+__global__ __launch_bounds__(kBlock) void k_state_scatter(Buf x, const Ctl* __restrict__ ctl, int p,
+                                                        const int32_t* __restrict__ blockoff,
                                                         int32_t* __restrict__ frontier,
-                                                        LiveWord* __restrict__ livew) {
+                                                        const LiveWord* __restrict__ livew) {
     __shared__ int s_wave[kBlock / 64];
     if (ctl->done) return;
     int32_t lo, hi;
@@ -431,37 +459,14 @@ __global__ __launch_bounds__(kBlock) void k_state_scatter(Buf x, BatchCtx b, con
     for (int32_t t0 = lo; t0 < hi; t0 += kBlock) {
         const int32_t i = t0 + (int32_t)threadIdx.x;
         const int32_t w0 = i - lane;
-        const bool gone = state_wave_done(x, b, w0, min(w0 + 63, hi - 1));
-        const int32_t d = i < hi && !gone ? x.S[i] : kDead;
-        const bool kr = i < hi && !gone && state_dying(d, state_thr(x, b, thr, i));  // removed
-        const bool k = kr && state_listed(d);                                          // listed for the peel
-        if (b.thrv && !gone) {
-            // per-graph counts of the removed edges: a graph's edges are
-            // consecutive, so a segmented sum over the wave gives one atomic
-            // per graph piece
-            const int32_t key = i < hi ? b.gidv[x.src[i]] : -1;
-            int32_t v = kr ? 1 : 0;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int32_t u = __shfl_up(v, o);
-                const int32_t kk = __shfl_up(key, o);
-                if (lane >= o && kk == key) v += u;
-            }
-            const int32_t next = __shfl_down(key, 1);
-            if (i < hi && v && (lane == 63 || next != key)) atomicAdd(&b.low_cnt[key], v);
-        }
+        const unsigned long long dying = w0 < hi ? livew[w0 >> 6].dying : 0ull;
+        const bool kr = i < hi && ((dying >> lane) & 1ull);
+        const int32_t d = kr ? x.S[i] : 0;
+        const bool k = kr && state_listed(d);
         int tot;
         const int32_t q = base + block_excl_flag<kBlock>(k, s_wave, tot);
-        if (kr) {
-            x.S[i] = kDying;
-            if (k) frontier[q] = i;
-        } else if (d == kDying) {
-            x.S[i] = kDead;
-        }
-        // the round's liveness words (i is the first of its wave's 64 positions on lane 0)
-        const unsigned long long dead = __ballot(i < hi && (d == kDead || d == kDying));
-        const unsigned long long dying = __ballot(kr);
-        if (__lane_id() == 0 && i < hi && !gone) livew[i >> 6] = LiveWord{dead, dying};
+        if (kr) x.S[i] = kDying;
+        if (k) frontier[q] = i;
         base += tot;
     }
 }
@@ -510,10 +515,10 @@ __global__ __launch_bounds__(kBlock) void k_state_graphs(BatchCtx b, int32_t G, 
 hipError_t launch_state_mark(const Buf& x, const BatchCtx& b, int32_t G, int32_t thr, int32_t* frontier, Scratch& sc,
                              Ctl* ctl, int p, int32_t m_hint, hipStream_t s) {
     const int32_t grid = filter_grid(m_hint);
-    k_state_count<<<grid, kBlock, 0, s>>>(x, b, ctl, p, thr, sc.blockcnt, sc.blockcnt2);
+    LiveWord* livew = reinterpret_cast<LiveWord*>(sc.keepw);
+    k_state_count<<<grid, kBlock, 0, s>>>(x, b, ctl, p, thr, sc.blockcnt, sc.blockcnt2, livew);
     k_state_scan<<<1, kScanThreads, 0, s>>>(sc.blockcnt, sc.blockcnt2, sc.blockoff, grid, ctl);
-    k_state_scatter<<<grid, kBlock, 0, s>>>(x, b, ctl, p, thr, sc.blockoff, frontier,
-                                            reinterpret_cast<LiveWord*>(sc.keepw));
+    k_state_scatter<<<grid, kBlock, 0, s>>>(x, ctl, p, sc.blockoff, frontier, livew);
     if (b.thrv && G > 0) k_state_graphs<<<grid_for(G), kBlock, 0, s>>>(b, G, ctl);
     return hipGetLastError();
 }

@@ -128,9 +128,10 @@ __global__ __launch_bounds__(kBlock) void k_peel(Buf x, Buf y, Csc c, const Keep
 
 // ---- in-place rounds.  Between compactions the edges keep their positions
 // and their state lives in S: a support (>= 0) for an alive edge, kDying for
-// an edge removed by the current round's prune, kDead for one removed by an
-// earlier round.  A round marks the removed edges and lists them, decides,
-// and peels; nothing is moved, so the in-edge lists need no remap.
+// a removed one; the round's liveness words tell the edges removed by this
+// round's prune from those removed earlier.  A round marks the removed edges
+// and lists them, decides, and peels; nothing is moved, so the in-edge lists
+// need no remap.
 
 // One thread: the round's bookkeeping (pass count, fixpoint, survivors) and,
 // with ratio > 0, whether the frontier is left to a recomputation.

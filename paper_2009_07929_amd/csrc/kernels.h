@@ -55,9 +55,10 @@ hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* 
 hipError_t launch_state_round(const Buf& x, const Csc& c, int32_t thr, const BatchCtx& b, int32_t G,
                               int32_t* frontier, Scratch& sc, Ctl* ctl, int p, float ratio, int32_t m_hint,
                               hipStream_t s);
-// Its marking (k_compact.hip): alive edges of x with S < thr become kDying
-// and are listed in frontier (Ctl::front_n of them), the previous round's
-// kDying edges become kDead; the batched form's per-graph pass counts.
+// Its marking (k_compact.hip): alive edges of x with S < thr become kDying,
+// those with S > 0 are listed in frontier (Ctl::front_n of them; Ctl::
+// removed_now counts all), the round's liveness words are written; the
+// batched form's per-graph pass counts.
 hipError_t launch_state_mark(const Buf& x, const BatchCtx& b, int32_t G, int32_t thr, int32_t* frontier, Scratch& sc,
                              Ctl* ctl, int p, int32_t m_hint, hipStream_t s);
 hipError_t launch_peel(const Buf& x, const Buf& y, const Csc& c, const KeepWord* keepw, const int32_t* frontier,
