@@ -467,11 +467,9 @@ RunSpec make_spec(int32_t n, int32_t m, const int32_t* rowptr, const int32_t* co
 // peel (the full neighbourhoods of a removed edge's ends).
 bool csc_needed(const RunSpec& r) { return uses_csc(r.sched) || r.incremental != 0; }
 
-PeelSpec peel_of(const RunSpec& r) {
-    PeelSpec pk{};
-    pk.on = r.incremental != 0;
-    pk.ratio = r.incremental == 2 ? (r.tuning.peel_ratio > 0.f ? r.tuning.peel_ratio : kDefaultPeelRatio) : 0.f;
-    return pk;
+// Incremental mode 2's frontier bound (0 in mode 1: every prune peels).
+float peel_ratio_of(const RunSpec& r) {
+    return r.incremental == 2 ? (r.tuning.peel_ratio > 0.f ? r.tuning.peel_ratio : kDefaultPeelRatio) : 0.f;
 }
 
 bool needs_features(const RunSpec& r) { return r.collect || (r.sched == KTRUSS_SCHED_LEARNED && r.mlp); }
@@ -497,49 +495,34 @@ int32_t set_up_run(const RunSpec& r, Work& w, hipStream_t s) {
     return KTRUSS_OK;
 }
 
-// Enqueues one prune round reading buffer p: support pass (unless `pass` is
-// false: incremental maintenance kept buffer p's supports current), per-graph
-// status (batched form), prune + compaction into buffer 1-p (with the peel
-// when incremental), preparation of the next pass (recompute mode).  No host
-// interaction: every kernel reads its counts from the control block and does
-// nothing once the fixpoint is reached.
-int32_t enqueue_round(const RunSpec& r, Work& w, int p, const PassDims& dm, hipStream_t s, bool pass = true) {
-    if (pass) {
-        int32_t rc = support_pass(r.sched, r.n, w, p, dm, s, r.collect ? w.sc.cycles : nullptr);
-        if (rc != KTRUSS_OK) return rc;
-        if (r.collect)
-            HIP_TRY(launch_append_costs(w.sc, r.n, r.capacity, r.out_x, r.out_y, w.ctl, s), "cost samples");
-    }
+// Enqueues one round of the recompute loop (Algorithm 1) reading buffer p:
+// support pass, per-graph status (batched form), prune + compaction into
+// buffer 1-p, preparation of the next pass.  No host interaction: every kernel
+// reads its counts from the control block and does nothing once the fixpoint
+// is reached.
+int32_t enqueue_round(const RunSpec& r, Work& w, int p, const PassDims& dm, hipStream_t s) {
+    int32_t rc = support_pass(r.sched, r.n, w, p, dm, s, r.collect ? w.sc.cycles : nullptr);
+    if (rc != KTRUSS_OK) return rc;
+    if (r.collect) HIP_TRY(launch_append_costs(w.sc, r.n, r.capacity, r.out_x, r.out_y, w.ctl, s), "cost samples");
     if (r.G > 0) HIP_TRY(launch_batch_status(w.b[p], w.batch, r.G, r.K, r.rounds_dev, w.ctl, s), "batch status");
     const bool csc = csc_needed(r);
     HIP_TRY(launch_compact(w.b[p], w.b[1 - p], csc ? &w.c[p] : nullptr, csc ? &w.c[1 - p] : nullptr, r.n, 0, r.thr,
-                           nullptr, w.batch, w.sc, w.ctl, p, dm.m, r.m, peel_of(r), s),
+                           nullptr, w.batch, w.sc, w.ctl, p, dm.m, r.m, s),
             "prune launch");
-    return r.incremental ? KTRUSS_OK : prepare(r, w, 1 - p, dm.m, s);
+    return prepare(r, w, 1 - p, dm.m, s);
 }
 
-// Host-checked rounds from buffer p until the fixpoint.  ready: buffer p is
-// prepared for a support pass and h holds its dimensions; otherwise (the
-// incremental mode after a compaction) its supports are current, unless the
-// peel was skipped (h.need_support), when they are zeroed and recomputed.
-int32_t host_rounds(const RunSpec& r, Work& w, int p, int32_t m_hint, bool ready, Ctl& h, hipStream_t s) {
-    int32_t rc;
+// Host-checked rounds of the recompute loop from buffer p (prepared for a
+// support pass, h holding its dimensions) until the fixpoint.
+int32_t host_rounds(const RunSpec& r, Work& w, int p, int32_t m_hint, Ctl& h, hipStream_t s) {
     for (;;) {
-        if (!ready && h.need_support) {
-            HIP_TRY(launch_zero_support(w.b[p], w.ctl, p, m_hint, s), "zero supports");
-            rc = prepare(r, w, p, m_hint, s);
-            if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
-            if (rc != KTRUSS_OK) return rc;
-            ready = true;
-        }
         const PassDims dm{m_hint, h.n_items, h.n_wave, h.n_thread};
-        rc = enqueue_round(r, w, p, dm, s, ready);
+        int32_t rc = enqueue_round(r, w, p, dm, s);
         if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
         if (rc != KTRUSS_OK) return rc;
         if (h.done) return KTRUSS_OK;
         m_hint = h.m_buf[1 - p];
         p ^= 1;
-        ready = !r.incremental;  // recompute mode: enqueue_round prepared the next pass
     }
 }
 
@@ -604,7 +587,7 @@ int32_t state_rounds_graph(const RunSpec& r, Work& w, int p, int32_t m_hint, Ctl
 // there.
 int32_t state_rounds(const RunSpec& r, Work& w, int p, int32_t m_hint, Ctl& h, hipStream_t s) {
     if (r.tuning.rounds_per_sync >= 2) return state_rounds_graph(r, w, p, m_hint, h, s);
-    const float ratio = peel_of(r).ratio;
+    const float ratio = peel_ratio_of(r);
     for (;;) {
         HIP_TRY(launch_state_round(w.b[p], w.c[p], r.thr, w.batch, r.G, w.sc.thread_tasks, w.sc, w.ctl, p, ratio,
                                    m_hint, s),
@@ -617,7 +600,7 @@ int32_t state_rounds(const RunSpec& r, Work& w, int p, int32_t m_hint, Ctl& h, h
             // and peeling stop walking them
             if ((int64_t)2 * h.kept < (int64_t)h.m_buf[p]) {
                 HIP_TRY(launch_compact(w.b[p], w.b[1 - p], &w.c[p], &w.c[1 - p], r.n, 3, r.thr, nullptr, w.batch, w.sc,
-                                       w.ctl, p, m_hint, r.m, PeelSpec{}, s),
+                                       w.ctl, p, m_hint, r.m, s),
                         "survivor compaction");
                 p ^= 1;
                 rc = read_ctl(w, h, s);
@@ -627,7 +610,7 @@ int32_t state_rounds(const RunSpec& r, Work& w, int p, int32_t m_hint, Ctl& h, h
             continue;
         }
         HIP_TRY(launch_compact(w.b[p], w.b[1 - p], &w.c[p], &w.c[1 - p], r.n, 2, r.thr, nullptr, w.batch, w.sc, w.ctl,
-                               p, m_hint, r.m, PeelSpec{}, s),
+                               p, m_hint, r.m, s),
                 "survivor compaction");
         p ^= 1;
         rc = prepare(r, w, p, m_hint, s);
@@ -655,23 +638,9 @@ int32_t run_rounds(const RunSpec& r, Work& w, hipStream_t s, Ctl& h) {
         return rc == KTRUSS_OK ? state_rounds(r, w, 0, r.m, h, s) : rc;
     }
     const int rps = r.tuning.rounds_per_sync;
-    if (rps <= 1) return host_rounds(r, w, 0, r.m, true, h, s);
-    int p = 0;
-    int32_t m_hint = r.m;
-    RunSpec rg = r;
-    if (r.incremental) {
-        // the first pass computes the supports on the host loop; the captured
-        // rounds only prune and peel.  Every prune peels, the first one too: a
-        // skipped peel would need a recomputation, which cannot be decided
-        // inside the graph (mode 2 runs as mode 1 here)
-        rg.incremental = 1;
-        const PassDims d1{m_hint, h.n_items, h.n_wave, h.n_thread};
-        rc = enqueue_round(rg, w, 0, d1, s, true);
-        if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
-        if (rc != KTRUSS_OK || h.done) return rc;
-        m_hint = h.m_buf[1];
-        p = 1;
-    }
+    if (rps <= 1) return host_rounds(r, w, 0, r.m, h, s);
+    const int p = 0;
+    const int32_t m_hint = r.m;
     // hipGraph mode: two rounds (p -> 1-p -> p) captured once with upper-bound
     // grids, replayed ceil(rps / 2) times between host checks.
     hipError_t e;
@@ -682,8 +651,8 @@ int32_t run_rounds(const RunSpec& r, Work& w, hipStream_t s, Ctl& h) {
     hipGraphExec_t exec = nullptr;
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "begin capture");
     t_capturing = true;
-    rc = enqueue_round(rg, w, p, dm, cs, !rg.incremental);
-    if (rc == KTRUSS_OK) rc = enqueue_round(rg, w, 1 - p, dm, cs, !rg.incremental);
+    rc = enqueue_round(r, w, p, dm, cs);
+    if (rc == KTRUSS_OK) rc = enqueue_round(r, w, 1 - p, dm, cs);
     t_capturing = false;
     hipError_t ec = hipStreamEndCapture(cs, &graph);
     if (rc != KTRUSS_OK) {
@@ -868,7 +837,7 @@ int32_t ktruss_support(const ktruss_graph* g, const uint8_t* alive, int32_t* sup
     int p = 0;
     if (alive) {
         HIP_TRY(launch_compact(w.b[0], w.b[1], csc ? &w.c[0] : nullptr, csc ? &w.c[1] : nullptr, n, 1, 0, alive,
-                               w.batch, w.sc, w.ctl, 0, m, m, PeelSpec{}, s),
+                               w.batch, w.sc, w.ctl, 0, m, m, s),
                 "restrict to alive");
         p = 1;
         HIP_TRY(launch_set_final(w.ctl, 1, s), "final buffer");
@@ -1002,14 +971,13 @@ int32_t ktruss_decompose(const ktruss_graph* g, int32_t* trussness, int32_t* k_m
         }
         const bool csc = csc_needed(r);
         HIP_TRY(launch_compact(w.b[f], w.b[1 - f], csc ? &w.c[f] : nullptr, csc ? &w.c[1 - f] : nullptr, r.n, 0, r.thr,
-                               nullptr, w.batch, w.sc, w.ctl, f, mf, r.m, peel_of(r), s),
+                               nullptr, w.batch, w.sc, w.ctl, f, mf, r.m, s),
                 "level prune");
-        rc = r.incremental ? KTRUSS_OK : prepare(r, w, 1 - f, mf, s);
+        rc = prepare(r, w, 1 - f, mf, s);
         if (rc == KTRUSS_OK) rc = read_ctl(w, h, s);
         if (rc != KTRUSS_OK) return rc;
-        // something was removed: rounds from buffer 1-f (recomputed, or kept
-        // current by the peel) until the fixpoint
-        if (!h.done) rc = host_rounds(r, w, 1 - f, h.m_buf[1 - f], !r.incremental, h, s);
+        // something was removed: recompute rounds from buffer 1-f until the fixpoint
+        if (!h.done) rc = host_rounds(r, w, 1 - f, h.m_buf[1 - f], h, s);
         if (rc != KTRUSS_OK) return rc;
     }
     HIP_TRY(hipStreamSynchronize(s), "decompose sync");

@@ -119,8 +119,9 @@ struct HubItem {
 
 // Keep flags of a compaction, 64 elements to a word, with the number of kept
 // elements before the word: element e's new position is pref plus the kept
-// bits below e's bit.  A 16-byte entry per 64 elements, so scattered lookups
-// of new positions hit a table 1/16 the size of a per-element one.
+// bits below e's bit.  A 16-byte entry per 64 elements, so the scattered
+// lookups of the in-edge list remap hit a table 1/16 the size of a
+// per-element one.
 struct alignas(16) KeepWord {
     unsigned long long bits;
     int32_t pref;

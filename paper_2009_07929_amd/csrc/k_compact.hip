@@ -26,23 +26,18 @@ __device__ __forceinline__ bool round_keep(const Buf& x, const BatchCtx& b, int3
 }
 
 // A policy reads what element i needs once (load), decides on it (keep) and
-// writes the survivor (emit) or handles the dropped element (drop).
-// frontier: when not null (incremental maintenance), the survivors keep their
-// supports and every removed edge's position is listed (frontier[i - q] for
-// element i with q survivors before it), in order; otherwise supports restart
-// at 0 for the next pass.
+// writes the survivor (emit) or handles the dropped element (drop).  The
+// recompute loop's prune: supports restart at 0 for the next pass.
 struct CsrRound {
     Buf x, y;
     int32_t thr;
     BatchCtx b;
-    int32_t* frontier;
     __device__ int32_t load(int32_t e) const { return e; }
     __device__ bool keep(int32_t e) const { return round_keep(x, b, thr, e); }
-    __device__ void drop(int32_t e, int32_t i, int32_t q) const {
+    __device__ void drop(int32_t e, int32_t, int32_t) const {
         // an edge of a graph finished in this pass leaves the working set
-        // without leaving its truss: it destroys no triangle (-1 in the list)
+        // without leaving its truss
         const bool finished = b.thrv && b.done_now[b.gidv[x.src[e]]];
-        if (frontier) frontier[i - q] = finished ? -1 : e;
         if (finished) {
             const int32_t c = x.eid[e];
             b.mask[c] = 1;
@@ -53,7 +48,7 @@ struct CsrRound {
         y.col[q] = x.col[e];
         y.src[q] = x.src[e];
         y.eid[q] = x.eid[e];
-        y.S[q] = frontier ? x.S[e] : 0;
+        y.S[q] = 0;
     }
 };
 
@@ -525,26 +520,20 @@ hipError_t launch_state_mark(const Buf& x, const BatchCtx& b, int32_t G, int32_t
 
 hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* cy, int32_t n, int mode, int32_t thr,
                           const uint8_t* alive_can, const BatchCtx& b, Scratch& sc, Ctl* ctl, int p, int32_t m_hint,
-                          int32_t csc_hint, const PeelSpec& peel, hipStream_t s) {
+                          int32_t csc_hint, hipStream_t s) {
     const int round = mode != 1;  // modes 0, 2, 3 skip their work once the run is done
     const bool batch = b.thrv != nullptr;
-    const bool inc = peel.on && mode == 0 && cx;
     if (mode == 0) {
-        run_filter(CsrRound{x, y, thr, b, inc ? sc.thread_tasks : nullptr}, ctl, p, batch ? 3 : 1, 1, sc.blockcnt,
-                   sc.blockoff, sc.xscan, sc.keepw, m_hint, s);
-    } else if (mode == 2) {
-        run_filter(CsrRound{x, y, thr, b, nullptr}, ctl, p, 2, 1, sc.blockcnt, sc.blockoff, sc.xscan, sc.keepw,
+        run_filter(CsrRound{x, y, thr, b}, ctl, p, batch ? 3 : 1, 1, sc.blockcnt, sc.blockoff, sc.xscan, sc.keepw,
                    m_hint, s);
+    } else if (mode == 2) {
+        run_filter(CsrRound{x, y, thr, b}, ctl, p, 2, 1, sc.blockcnt, sc.blockoff, sc.xscan, sc.keepw, m_hint, s);
     } else if (mode == 3) {
         run_filter(CsrLive{x, y, b}, ctl, p, 2, 1, sc.blockcnt, sc.blockoff, sc.xscan, sc.keepw, m_hint, s);
     } else {
         run_filter(CsrAlive{x, y, alive_can}, ctl, p, 2, 0, sc.blockcnt, sc.blockoff, sc.xscan, sc.keepw, m_hint, s);
     }
     k_ptr_remap<<<grid_for((int64_t)n + 1), kBlock, 0, s>>>(x.rowptr, y.rowptr, n, sc.xscan, ctl, round);
-    if (inc) {  // on the round's graph: buffer p's rows and the in-edge lists before their remap
-        const hipError_t e = launch_peel(x, y, *cx, sc.keepw, sc.thread_tasks, ctl, p, peel.ratio, m_hint, s);
-        if (e != hipSuccess) return e;
-    }
     if (cx && csc_hint > 0) {  // the in-edge lists (one set: cy names the same arrays) and alive in-edge counts
         k_zero_rows<<<grid_for(n), kBlock, 0, s>>>(sc.alive_in, n, ctl, round);
         k_csc_remap<<<min(grid_for(csc_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(cx->edge, cx->key, sc.keepw,

@@ -97,35 +97,6 @@ __device__ __forceinline__ void peel_triangles(const Buf& x, const Csc& c, int32
     wave_common(f + 1, ru1, row_val, row_edge, rv0, rv1, row_val, row_edge, charge);
 }
 
-// Peel after a compaction: x is the round's graph, y the compacted survivors.
-__global__ __launch_bounds__(kBlock) void k_peel(Buf x, Buf y, Csc c, const KeepWord* __restrict__ keepw,
-                                               const int32_t* __restrict__ frontier, Ctl* ctl, int p,
-                                               float ratio) {
-    if (ctl->done) return;
-    const int32_t nf = ctl->m_buf[p] - ctl->kept;  // edges removed by this prune
-    // auto mode: a frontier larger than ratio x the survivors is left to a
-    // recomputation (the next round runs a support pass instead)
-    if (ratio > 0.f && (double)nf > (double)ratio * (double)ctl->kept) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) ctl->need_support = 1;
-        return;
-    }
-    const int32_t nw = (int32_t)(gridDim.x * (kBlock / 64));
-    for (int32_t wid = (int32_t)((blockIdx.x * kBlock + threadIdx.x) >> 6); wid < nf; wid += nw) {
-        const int32_t f = frontier[wid];
-        if (f < 0) continue;  // an edge of a finished graph (batched form): its triangles stay
-        // charge the triangle (f, e1, e2) here unless a removed edge with a
-        // smaller position is in it; decrement its surviving edges
-        auto charge = [&](int32_t e1, int32_t e2) {
-            if (e1 < 0 || e2 < 0) return;  // an edge removed in an earlier round: not a triangle of this round
-            const int32_t q1 = keep_rank(keepw, e1), q2 = keep_rank(keepw, e2);
-            if ((q1 < 0 && e1 < f) || (q2 < 0 && e2 < f)) return;
-            if (q1 >= 0) atomicSub(&y.S[q1], 1);
-            if (q2 >= 0) atomicSub(&y.S[q2], 1);
-        };
-        peel_triangles(x, c, f, charge);
-    }
-}
-
 // ---- in-place rounds.  Between compactions the edges keep their positions
 // and their state lives in S: a support (>= 0) for an alive edge, kDying for
 // a removed one; the round's liveness words tell the edges removed by this
@@ -177,16 +148,6 @@ __global__ __launch_bounds__(kBlock) void k_peel_state(Buf x, Csc c, const int32
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_zero_support(Buf x, const Ctl* __restrict__ ctl, int p) {
-    const int32_t m = ctl->m_buf[p];
-    for (int32_t e = (int32_t)(blockIdx.x * kBlock + threadIdx.x); e < m; e += (int32_t)(gridDim.x * kBlock))
-        x.S[e] = 0;
-}
-
-__global__ void k_need_support_clear(Ctl* ctl) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->need_support = 0;
-}
-
 }  // namespace
 
 hipError_t launch_state_round(const Buf& x, const Csc& c, int32_t thr, const BatchCtx& b, int32_t G,
@@ -203,19 +164,6 @@ hipError_t launch_state_round(const Buf& x, const Csc& c, int32_t thr, const Bat
     return hipGetLastError();
 }
 
-hipError_t launch_peel(const Buf& x, const Buf& y, const Csc& c, const KeepWord* keepw, const int32_t* frontier,
-                       Ctl* ctl, int p, float ratio, int32_t m_hint, hipStream_t s) {
-    if (m_hint <= 0) return hipSuccess;
-    k_need_support_clear<<<1, 64, 0, s>>>(ctl);
-    const unsigned grid = min(grid_for((int64_t)m_hint * 64), (unsigned)kStreamMaxGrid);
-    k_peel<<<grid, kBlock, 0, s>>>(x, y, c, keepw, frontier, ctl, p, ratio);
-    return hipGetLastError();
-}
 
-hipError_t launch_zero_support(const Buf& x, const Ctl* ctl, int p, int32_t m_hint, hipStream_t s) {
-    if (m_hint <= 0) return hipSuccess;
-    k_zero_support<<<min(grid_for(m_hint), (unsigned)kStreamMaxGrid), kBlock, 0, s>>>(x, ctl, p);
-    return hipGetLastError();
-}
 
 }  // namespace kt

@@ -33,21 +33,11 @@ hipError_t launch_prune_canonical(const int32_t* support, uint8_t* alive, int32_
 // graphs finished in this pass are written to the outputs and dropped, and
 // the run ends when no edge is left.  m_hint bounds the alive edges, csc_hint
 // the in-edge list entries (the run's m: removed edges stay as tombstones).
-// Incremental support maintenance of a prune round (mode 0, one graph, with
-// in-edge lists): the survivors keep their supports, the removed edges are
-// listed (in Scratch::thread_tasks) and k_peel takes the destroyed triangles
-// off the survivors' supports.  ratio > 0: the peel is skipped, and
-// Ctl::need_support set, when more than ratio x the survivors were removed.
-struct PeelSpec {
-    bool on;
-    float ratio;
-};
 hipError_t launch_compact(const Buf& x, const Buf& y, const Csc* cx, const Csc* cy, int32_t n, int mode, int32_t thr,
                           const uint8_t* alive_can, const BatchCtx& b, Scratch& sc, Ctl* ctl, int p, int32_t m_hint,
-                          int32_t csc_hint, const PeelSpec& peel, hipStream_t s);
-// The peel itself (k_peel.hip), on buffer x's graph, survivors' supports in y.
-// One in-place prune round of incremental maintenance on buffer x (no
-// compaction): removed edges marked and listed in frontier, bookkeeping in
+                          int32_t csc_hint, hipStream_t s);
+// One in-place prune round of incremental maintenance on buffer x (k_peel.hip;
+// no compaction): removed edges marked and listed in frontier, bookkeeping in
 // ctl, then their triangles peeled unless ratio > 0 and the frontier exceeds
 // ratio x the survivors (ctl->need_support).
 // With a batch context (b.thrv set) the threshold is per graph and every
@@ -61,11 +51,6 @@ hipError_t launch_state_round(const Buf& x, const Csc& c, int32_t thr, const Bat
 // batched form's per-graph pass counts.
 hipError_t launch_state_mark(const Buf& x, const BatchCtx& b, int32_t G, int32_t thr, int32_t* frontier, Scratch& sc,
                              Ctl* ctl, int p, int32_t m_hint, hipStream_t s);
-hipError_t launch_peel(const Buf& x, const Buf& y, const Csc& c, const KeepWord* keepw, const int32_t* frontier,
-                       Ctl* ctl, int p, float ratio, int32_t m_hint, hipStream_t s);
-// Zeroes the supports of buffer p's alive edges (a recomputation follows a
-// round whose compaction kept them).
-hipError_t launch_zero_support(const Buf& x, const Ctl* ctl, int p, int32_t m_hint, hipStream_t s);
 
 // ---- batched form (k_batch.hip)
 hipError_t launch_batch_setup(const BatchCtx& b, int32_t G, int32_t n_total, const int32_t* K, const int32_t* src,
