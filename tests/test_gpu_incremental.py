@@ -54,7 +54,7 @@ def run(rp, col, K, schedule, incremental, ratio=0, rps=0):
 def test_incremental_matches_oracle(idx):
     name, (n, s, d) = GRAPHS[idx]
     rp, col, _ = kt().ktruss_build_csr(s, d, n)
-    for K in (3, 4, 6, 9, 14):
+    for K in (2, 3, 4, 6, 9, 14, 1000):  # 2: nothing can go; 1000: everything goes
         om, osup, orounds = oracle.truss(rp, col, K, "P")
         for sched in (0, 1, 4, 5):
             for inc, ratio, rps in ((1, 0, 0), (2, 1, 0), (2, 4, 0), (2, 0.25, 0), (1, 0, 3), (2, 0.25, 4)):
