@@ -402,19 +402,60 @@ __global__ __launch_bounds__(kHubThreads) void k_support_hub(Buf x, Csc c, const
 
 // 64x64 bit transpose across a wave: lane j holds row j (bit l = entry
 // (j, l)); afterwards lane l holds column l (bit j = entry (j, l)).  Six
-// butterfly stages swap the off-diagonal blocks of halving size.
-__device__ __forceinline__ unsigned long long transpose64(unsigned long long v, int lane) {
-    const unsigned long long keep[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
-                                        0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
-#pragma unroll
-    for (int st = 0; st < 6; ++st) {
-        const int b = 32 >> st;
-        const unsigned long long m = keep[st];
-        const uint32_t lo = __shfl_xor((uint32_t)v, b), hi = __shfl_xor((uint32_t)(v >> 32), b);
-        const unsigned long long y = ((unsigned long long)hi << 32) | lo;
-        v = (lane & b) ? ((v & ~m) | ((y & ~m) >> b)) : ((v & m) | ((y & m) << b));
+// butterfly stages swap the off-diagonal blocks of halving size: at stage b a
+// lane without bit b of its index keeps the bits whose index lacks bit b and
+// takes its partner's (lane xor b) such bits moved up by b; a lane with bit b
+// does the mirror image.  The 64-bit rows are handled as two 32-bit halves:
+// stage 32 exchanges whole halves (one word sent per lane: the half its
+// partner needs), the other stages work within each half.  Partners within
+// a row of 16 lanes are read with DPP (quad permutes for 1 and 2, rotates of
+// the row for 4 and 8), the partner 16 lanes away with a swizzle and the one
+// 32 lanes away with a permute; the move by b is a rotate (the bits it wraps
+// around fall outside the kept mask) and the merge one bit-field select.
+template <int B>
+__device__ __forceinline__ uint32_t lane_xor(uint32_t v, int lane) {
+    if constexpr (B == 1) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);  // quad_perm [1,0,3,2]
+    } else if constexpr (B == 2) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);  // quad_perm [2,3,0,1]
+    } else if constexpr (B == 4) {
+        // row_ror:n reads lane (l - n) mod 16 of the row: n = 4 for lanes with bit 2, 12 for the others
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xF, 0xF, false);
+        const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x12C, 0xF, 0xF, false);
+        return (lane & 4) ? dn : up;
+    } else if constexpr (B == 8) {
+        return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xF, 0xF, false);  // row_ror:8
+    } else {
+        static_assert(B == 16, "lanes 32 apart go through the permute in transpose64");
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);  // bit-mask mode: lane xor 16
     }
-    return v;
+}
+
+template <int B>
+__device__ __forceinline__ void transpose_stage(uint32_t& lo, uint32_t& hi, int lane) {
+    constexpr uint32_t m = B == 16 ? 0x0000FFFFu : B == 8 ? 0x00FF00FFu : B == 4 ? 0x0F0F0F0Fu
+                         : B == 2 ? 0x33333333u : 0x55555555u;  // the bits whose index lacks bit B
+    const bool up = (lane & B) != 0;
+    const uint32_t keep = up ? ~m : m;
+    const uint32_t rot = up ? (uint32_t)B : (uint32_t)(32 - B);  // rotate right: >> B, or << B
+    const uint32_t ylo = lane_xor<B>(lo, lane), yhi = lane_xor<B>(hi, lane);
+    lo = (lo & keep) | (__builtin_amdgcn_alignbit(ylo, ylo, rot) & ~keep);
+    hi = (hi & keep) | (__builtin_amdgcn_alignbit(yhi, yhi, rot) & ~keep);
+}
+
+__device__ __forceinline__ unsigned long long transpose64(unsigned long long v, int lane) {
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+    {  // stage 32: a lane in the lower half takes its partner's low half as its high half, and vice versa
+        const bool up = (lane & 32) != 0;
+        const uint32_t r = (uint32_t)__shfl_xor((int)(up ? lo : hi), 32);
+        if (up) lo = r; else hi = r;
+    }
+    transpose_stage<16>(lo, hi, lane);
+    transpose_stage<8>(lo, hi, lane);
+    transpose_stage<4>(lo, hi, lane);
+    transpose_stage<2>(lo, hi, lane);
+    transpose_stage<1>(lo, hi, lane);
+    return ((unsigned long long)hi << 32) | lo;
 }
 
 // Row-local sum of the hub kernel's hit words: S(i, w) of the edge at
