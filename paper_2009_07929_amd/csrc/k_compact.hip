@@ -225,7 +225,8 @@ __global__ __launch_bounds__(kBlock) void k_zero_rows(int32_t* __restrict__ a, i
 // removed one); entries of removed edges, and tombstones, stay -1.  The alive
 // entries of every row kappa are counted on the way (alive_in, zeroed
 // before): the lists are grouped by kappa (key), so a wave-level segmented
-// sum adds each run and its last lane issues one atomic per run piece.
+// sum adds each run and its last lane issues one atomic per run piece (a
+// wave inside one run: a popcount and one atomic).
 __global__ __launch_bounds__(kBlock) void k_csc_remap(int32_t* __restrict__ cedge, const int32_t* __restrict__ ckey,
                                                     const KeepWord* __restrict__ keepw, int32_t* __restrict__ alive_in,
                                                     const Ctl* __restrict__ ctl, int round) {
@@ -245,6 +246,14 @@ __global__ __launch_bounds__(kBlock) void k_csc_remap(int32_t* __restrict__ cedg
                 v = q >= 0;
             }
             key = ckey[c];
+        }
+        // keys never decrease along the lists (-1 past the end): equal keys at
+        // both ends put the wave in one row's list, counted by one popcount
+        const int32_t k_first = __builtin_amdgcn_readfirstlane(key);
+        if (k_first >= 0 && k_first == __builtin_amdgcn_readlane(key, 63)) {
+            const int32_t n_alive = (int32_t)__popcll(__ballot(v != 0));
+            if (lane == 0 && n_alive) atomicAdd(&alive_in[k_first], n_alive);
+            continue;
         }
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
@@ -399,18 +408,27 @@ __global__ __launch_bounds__(kBlock) void k_state_count(Buf x, BatchCtx b, const
         c += k;
         if (b.thrv && !gone) {
             // per-graph counts of the removed edges: a graph's edges are
-            // consecutive, so a segmented sum over the wave gives one atomic
-            // per graph piece
+            // consecutive, so the graph ids along the wave never decrease (-1
+            // past the end).  Equal ids at both ends put the whole wave in one
+            // graph (the usual case): one popcount and one atomic.  Otherwise
+            // a segmented sum over the wave gives one atomic per graph piece.
             const int32_t key = i < hi ? b.gidv[x.src[i]] : -1;
-            int32_t v = kr ? 1 : 0;
+            const int32_t k_first = __builtin_amdgcn_readfirstlane(key);
+            const int32_t k_last = __builtin_amdgcn_readlane(key, 63);
+            if (k_first == k_last && k_first >= 0) {
+                const int32_t n_kr = (int32_t)__popcll(__ballot(kr));
+                if (lane == 0 && n_kr) atomicAdd(&b.low_cnt[k_first], n_kr);
+            } else {
+                int32_t v = kr ? 1 : 0;
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int32_t u = __shfl_up(v, o);
-                const int32_t kk = __shfl_up(key, o);
-                if (lane >= o && kk == key) v += u;
+                for (int o = 1; o < 64; o <<= 1) {
+                    const int32_t u = __shfl_up(v, o);
+                    const int32_t kk = __shfl_up(key, o);
+                    if (lane >= o && kk == key) v += u;
+                }
+                const int32_t next = __shfl_down(key, 1);
+                if (i < hi && v && (lane == 63 || next != key)) atomicAdd(&b.low_cnt[key], v);
             }
-            const int32_t next = __shfl_down(key, 1);
-            if (i < hi && v && (lane == 63 || next != key)) atomicAdd(&b.low_cnt[key], v);
         }
         const unsigned long long dead = __ballot(i < hi && d < 0);
         const unsigned long long dying = __ballot(kr);
