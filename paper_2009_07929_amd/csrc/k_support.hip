@@ -458,6 +458,14 @@ __device__ __forceinline__ unsigned long long transpose64(unsigned long long v, 
     return ((unsigned long long)hi << 32) | lo;
 }
 
+// Column counts of the wave's 64x64 bit matrix (lane l: how many rows have
+// bit l), by the transpose and a popcount; nothing to do when every row is
+// empty.  Called with the whole wave active.
+__device__ __forceinline__ uint32_t column_counts(unsigned long long v, int lane) {
+    if (__ballot(v != 0ull) == 0ull) return 0u;
+    return (uint32_t)__popcll(transpose64(v, lane));
+}
+
 // Row-local sum of the hub kernel's hit words: S(i, w) of the edge at
 // position p of row i gains one for every earlier task j of row i (a hub task:
 // hub_row[col[j]]) whose hit words have the bit of tail offset p - j - 1.
@@ -494,7 +502,7 @@ __global__ __launch_bounds__(kBlock) void k_hit_sum(Buf x, const unsigned long l
             if (w < hit_cap) v = hitw[w] << (lane + 1);
         }
     }
-    uint32_t add = (uint32_t)__popcll(transpose64(v, lane));
+    uint32_t add = column_counts(v, lane);
     const int32_t r0 = x.src[P0];  // the row holding P0
     const int32_t r0s = x.rowptr[r0], r0e = x.rowptr[r0 + 1];
     if (r0s < P0 && !is_long(r0e - r0s)) {
@@ -511,7 +519,7 @@ __global__ __launch_bounds__(kBlock) void k_hit_sum(Buf x, const unsigned long l
                 const unsigned long long hi = ((c + 1) * 64 < L && wc + 1 < hit_cap) ? hitw[wc + 1] : 0ull;
                 w = sft ? ((lo >> sft) | (hi << (64 - sft))) : lo;
             }
-            add += (uint32_t)__popcll(transpose64(w, lane));
+            add += column_counts(w, lane);
         }
     }
     if (p < m && add) x.S[p] += (int32_t)add;
@@ -570,7 +578,7 @@ __global__ __launch_bounds__(kBlock) void k_hit_sum_long(Buf x, const unsigned l
                 for (int u = 0; u < kHitLongUnroll; ++u) {
                     const unsigned long long v = (lane == 63 ? 0ull : (wd[u] << (lane + 1))) | (prev >> (63 - lane));
                     prev = wd[u];
-                    const uint32_t cnt = (uint32_t)__popcll(transpose64(v, lane));
+                    const uint32_t cnt = column_counts(v, lane);
                     if (cnt) atomicAdd(&s_cnt[64 * (b + c0 + u) + lane], (int32_t)cnt);
                 }
             }
